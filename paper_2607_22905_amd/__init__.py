@@ -1,0 +1,13 @@
+"""MI355X (gfx950) AlgMortar-PCG: the algebraic multiscale mortar preconditioner
+inside a conjugate gradient solve, as hand-written HIP kernels behind a C-ABI
+(include/algmortar.h).  This package is the thin Python binding.
+
+The library must be built first (``python -m paper_2607_22905_amd.build``);
+nothing here falls back to CPU code.
+"""
+from .solver import (AlgMortar, Tpfa, adjoint_grad, partition_blocks, partition_bisect,
+                     structure, structure_sizes)
+from ._lib import AlgMortarError, load
+
+__all__ = ["AlgMortar", "Tpfa", "adjoint_grad", "partition_blocks", "partition_bisect",
+           "structure", "structure_sizes", "AlgMortarError", "load"]

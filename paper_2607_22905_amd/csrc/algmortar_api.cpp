@@ -1,0 +1,846 @@
+// C-ABI of the AlgMortar-PCG library (include/algmortar.h): argument checks,
+// the set-up driver (Algorithm 1), the apply (Algorithm 2), the PCG driver
+// with hipGraph-captured chunks of iterations, and the differentiation form.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "algmortar.h"
+#include "am_device.h"
+#include "am_host.h"
+
+using namespace am;
+
+struct am_handle_s {
+  std::string err;
+  am_options opt{};
+  Structure st;
+  LocalPlan lp;
+  DeviceState d;
+  hipStream_t own = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double* tres = nullptr;  // [kMaxNRHS] ||b - Ax||^2
+  double* bp = nullptr;    // permuted right-hand side
+};
+
+struct am_tpfa_s {
+  std::string err;
+  TpfaDevice t;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+am_status fail(am_handle h, am_status s, const std::string& msg) {
+  if (h) h->err = msg;
+  g_err = msg;
+  return s;
+}
+
+#define HCHK(expr)                                                                         \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(h, e_ == hipErrorOutOfMemory ? AM_ERR_OOM : AM_ERR_HIP,                  \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                      \
+  } while (0)
+
+template <class T>
+hipError_t dalloc(std::vector<void*>& allocs, T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, count * sizeof(T));
+  if (e != hipSuccess) return e;
+  allocs.push_back(q);
+  *p = (T*)q;
+  return hipSuccess;
+}
+
+template <class T>
+hipError_t upload(std::vector<void*>& allocs, T** p, const std::vector<T>& v, hipStream_t s) {
+  hipError_t e = dalloc(allocs, p, v.size());
+  if (e != hipSuccess || v.empty()) return e;
+  e = hipMemcpyAsync(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(s);
+}
+
+int pow2_at_least(int x) {
+  int r = 1;
+  while (r < x) r *= 2;
+  return r;
+}
+
+am_status host_csr(const am_csr* A, HostCSR& H, std::vector<double>& vals, am_handle h) {
+  if (!A || !A->row_ptr || !A->col_idx || !A->val || A->n <= 0)
+    return fail(h, AM_ERR_ARG, "A: null pointer or empty matrix");
+  H.n = A->n;
+  H.nnz = A->nnz;
+  H.rp = A->row_ptr;
+  H.ci = A->col_idx;
+  if (A->values_on_device) {
+    vals.resize((size_t)A->nnz);
+    hipError_t e = hipMemcpy(vals.data(), A->val, sizeof(double) * (size_t)A->nnz,
+                             hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(h, AM_ERR_HIP, std::string("copy of A values: ") + hipGetErrorString(e));
+    H.v = vals.data();
+  } else {
+    H.v = A->val;
+  }
+  return AM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* algmortar_last_error(am_handle h) { return h ? h->err.c_str() : g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+am_status am_partition_blocks(int32_t nx, int32_t ny, int32_t nz, int32_t bx, int32_t by,
+                              int32_t bz, int32_t* part, int32_t* nparts) {
+  std::string e;
+  am_status s = partition_blocks(nx, ny, nz, bx, by, bz, part, nparts, e);
+  if (s != AM_OK) g_err = e;
+  return s;
+}
+
+am_status am_partition_bisect(const am_csr* A, int32_t lo, int32_t hi, uint64_t seed,
+                              int32_t* part, int32_t* nparts) {
+  if (!A || A->values_on_device) return fail(nullptr, AM_ERR_ARG, "A must be host resident");
+  HostCSR H;
+  std::vector<double> tmp;
+  am_status s = host_csr(A, H, tmp, nullptr);
+  if (s != AM_OK) return s;
+  std::string e;
+  s = validate_csr(H, e);
+  if (s != AM_OK) return fail(nullptr, s, e);
+  s = partition_bisect(H, lo, hi, seed, part, nparts, e);
+  if (s != AM_OK) g_err = e;
+  return s;
+}
+
+static am_status host_structure(const am_csr* A, const int32_t* part, int32_t nparts,
+                                int32_t mortar, Structure& st) {
+  if (!A || A->values_on_device) return fail(nullptr, AM_ERR_ARG, "A must be host resident");
+  HostCSR H;
+  std::vector<double> tmp;
+  am_status s = host_csr(A, H, tmp, nullptr);
+  if (s != AM_OK) return s;
+  std::string e;
+  if ((s = validate_csr(H, e)) != AM_OK) return fail(nullptr, s, e);
+  if ((s = validate_partition(H.n, part, nparts, e)) != AM_OK) return fail(nullptr, s, e);
+  if ((s = build_structure(H, part, nparts, mortar, st, e)) != AM_OK) return fail(nullptr, s, e);
+  return AM_OK;
+}
+
+am_status am_structure_sizes(const am_csr* A, const int32_t* part, int32_t nparts,
+                             int32_t mortar, int64_t* n_iface, int64_t* n_edges) {
+  if (!n_iface || !n_edges) return fail(nullptr, AM_ERR_ARG, "null output");
+  Structure st;
+  am_status s = host_structure(A, part, nparts, mortar, st);
+  if (s != AM_OK) return s;
+  *n_iface = st.n_iface();
+  *n_edges = st.n_edges();
+  return AM_OK;
+}
+
+static void copy_structure(const Structure& st, int32_t* perm, int64_t* sub_ptr,
+                           int64_t* iface_ptr, int32_t* iface_ij, int32_t* edge_k,
+                           int32_t* edge_l) {
+  if (perm) std::copy(st.perm.begin(), st.perm.end(), perm);
+  if (sub_ptr) std::copy(st.sub_ptr.begin(), st.sub_ptr.end(), sub_ptr);
+  if (iface_ptr) std::copy(st.iface_ptr.begin(), st.iface_ptr.end(), iface_ptr);
+  if (iface_ij) std::copy(st.iface_ij.begin(), st.iface_ij.end(), iface_ij);
+  if (edge_k) std::copy(st.edge_k.begin(), st.edge_k.end(), edge_k);
+  if (edge_l) std::copy(st.edge_l.begin(), st.edge_l.end(), edge_l);
+}
+
+am_status am_structure(const am_csr* A, const int32_t* part, int32_t nparts, int32_t mortar,
+                       int32_t* perm, int64_t* sub_ptr, int64_t* iface_ptr, int32_t* iface_ij,
+                       int32_t* edge_k, int32_t* edge_l) {
+  Structure st;
+  am_status s = host_structure(A, part, nparts, mortar, st);
+  if (s != AM_OK) return s;
+  copy_structure(st, perm, sub_ptr, iface_ptr, iface_ij, edge_k, edge_l);
+  return AM_OK;
+}
+
+// ---------------------------------------------------------------------------
+am_status algmortar_destroy(am_handle h) {
+  if (!h) return AM_OK;
+  const bool touched = h->own || !h->d.allocs.empty() || h->d.h_flags;
+  if (!touched) {  // failed in host validation: no device state to release
+    delete h;
+    return AM_OK;
+  }
+  hipSetDevice(h->d.device);
+  if (h->d.graph) hipGraphExecDestroy(h->d.graph);
+  for (void* p : h->d.allocs) hipFree(p);
+  if (h->d.h_flags) hipHostFree(h->d.h_flags);
+  if (h->ev0) hipEventDestroy(h->ev0);
+  if (h->ev1) hipEventDestroy(h->ev1);
+  if (h->own) hipStreamDestroy(h->own);
+  delete h;
+  return AM_OK;
+}
+
+am_status algmortar_setup(const am_csr* A, const int32_t* part, int32_t nparts,
+                          const am_options* opt_in, void* stream, am_handle* out) {
+  if (!out) return fail(nullptr, AM_ERR_ARG, "out is null");
+  *out = nullptr;
+  am_options opt{AM_FP64, AM_MORTAR_PER_INTERFACE, 1, 0, 0u};
+  if (opt_in) opt = *opt_in;
+  if (opt.local_prec < AM_FP64 || opt.local_prec > AM_BF16 || opt.mortar < 0 || opt.mortar > 1 ||
+      opt.max_nrhs < 1 || opt.max_nrhs > kMaxNRHS || opt.device < 0)
+    return fail(nullptr, AM_ERR_ARG, "invalid options");
+  am_handle h = new am_handle_s();
+  h->opt = opt;
+  auto bail = [&](am_status s) {
+    std::string msg = h->err;
+    algmortar_destroy(h);
+    g_err = msg;
+    return s;
+  };
+  HostCSR H;
+  std::vector<double> vals;
+  if (A && A->values_on_device) {
+    if (hipSetDevice(opt.device) != hipSuccess) {
+      fail(h, AM_ERR_HIP, "hipSetDevice failed");
+      return bail(AM_ERR_HIP);
+    }
+  }
+  am_status s = host_csr(A, H, vals, h);
+  if (s != AM_OK) return bail(s);
+  std::string e;
+  if ((s = validate_csr(H, e)) != AM_OK) { fail(h, s, e); return bail(s); }
+  if ((s = validate_partition(H.n, part, nparts, e)) != AM_OK) { fail(h, s, e); return bail(s); }
+  Structure& st = h->st;
+  LocalPlan& lp = h->lp;
+  if ((s = build_structure(H, part, nparts, opt.mortar, st, e)) != AM_OK) { fail(h, s, e); return bail(s); }
+  if ((s = plan_local(H, st, lp, e)) != AM_OK) { fail(h, s, e); return bail(s); }
+  if (lp.max_ni > 128) {
+    fail(h, AM_ERR_UNSUPPORTED, "a subdomain touches more than 128 mortar basis functions");
+    return bail(AM_ERR_UNSUPPORTED);
+  }
+
+  DeviceState& d = h->d;
+  d.device = opt.device;
+  d.prec = opt.local_prec;
+  d.n = H.n;
+  d.m = st.m;
+  d.NL = st.n_iface();
+  d.NE = st.n_edges();
+  d.ldS = (int32_t)((d.NL + kTile - 1) / kTile * kTile);
+  d.max_nrhs = pow2_at_least(opt.max_nrhs);
+
+  auto hipfail = [&](hipError_t he, const char* what) {
+    fail(h, he == hipErrorOutOfMemory ? AM_ERR_OOM : AM_ERR_HIP,
+         std::string(what) + ": " + hipGetErrorString(he));
+    return bail(he == hipErrorOutOfMemory ? AM_ERR_OOM : AM_ERR_HIP);
+  };
+#define SCHK(expr)                              \
+  do {                                          \
+    hipError_t he_ = (expr);                    \
+    if (he_ != hipSuccess) return hipfail(he_, #expr); \
+  } while (0)
+
+  SCHK(hipSetDevice(d.device));
+  SCHK(hipStreamCreateWithFlags(&h->own, hipStreamNonBlocking));
+  SCHK(hipEventCreate(&h->ev0));
+  SCHK(hipEventCreate(&h->ev1));
+  hipStream_t sm = h->own;
+  if (stream) SCHK(hipStreamSynchronize((hipStream_t)stream));
+
+  // ---- host-side layout ----
+  const int64_t n = d.n;
+  const std::vector<int32_t>& dperm = lp.dperm;
+  const std::vector<int32_t>& dpos = lp.dpos;
+  std::vector<int64_t> prp(n + 1, 0);
+  std::vector<int32_t> pci((size_t)H.nnz);
+  std::vector<double> pv((size_t)H.nnz);
+  int32_t w = 0;
+  {
+    std::vector<std::pair<int32_t, double>> row;
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t o = dperm[i];
+      row.clear();
+      for (int64_t p = H.rp[o]; p < H.rp[o + 1]; ++p) row.emplace_back(dpos[H.ci[p]], H.v[p]);
+      std::sort(row.begin(), row.end(),
+                [](const std::pair<int32_t, double>& a, const std::pair<int32_t, double>& b) {
+                  return a.first < b.first;
+                });
+      prp[i + 1] = prp[i] + (int64_t)row.size();
+      for (size_t t = 0; t < row.size(); ++t) {
+        pci[prp[i] + t] = row[t].first;
+        pv[prp[i] + t] = row[t].second;
+      }
+      w = std::max<int32_t>(w, (int32_t)row.size());
+    }
+  }
+  d.ell_w = w;
+  std::vector<int32_t> ell_col((size_t)w * n);
+  std::vector<double> ell_val((size_t)w * n, 0.0);
+  for (int64_t i = 0; i < n; ++i)
+    for (int32_t c = 0; c < w; ++c) {
+      const int64_t p = prp[i] + c;
+      if (p < prp[i + 1]) {
+        ell_col[(size_t)c * n + i] = pci[p];
+        ell_val[(size_t)c * n + i] = pv[p];
+      } else {
+        ell_col[(size_t)c * n + i] = (int32_t)i;
+      }
+    }
+  for (int bk = 0; bk < 2; ++bk) d.bucket_sub[bk].clear();
+  for (int32_t s2 = 0; s2 < st.m; ++s2) d.bucket_sub[lp.wp[s2] == 64 ? 0 : 1].push_back(s2);
+
+  const int64_t NL = d.NL;
+  const int64_t npair = 2 * NL;
+  std::vector<int32_t> pair_sub(npair), pair_q(npair);
+  std::vector<int64_t> bidx(npair);
+  for (int32_t s2 = 0; s2 < st.m; ++s2)
+    for (int64_t pi = st.isub_ptr[s2]; pi < st.isub_ptr[s2 + 1]; ++pi) {
+      pair_sub[pi] = s2;
+      pair_q[pi] = (int32_t)(pi - st.isub_ptr[s2]);
+      const int32_t nidx = st.isub_list[pi];
+      if (st.iface_ij[2 * nidx] == s2)
+        bidx[2 * nidx] = pi;
+      else
+        bidx[2 * nidx + 1] = pi;
+    }
+  for (int bk = 0; bk < 2; ++bk) d.bucket_pair[bk].clear();
+  for (int64_t pi = 0; pi < npair; ++pi)
+    d.bucket_pair[lp.wp[pair_sub[pi]] == 64 ? 0 : 1].push_back((int32_t)pi);
+  std::vector<int64_t> mbf_off(st.m + 1, 0);
+  for (int32_t s2 = 0; s2 < st.m; ++s2)
+    mbf_off[s2 + 1] = mbf_off[s2] + (st.isub_ptr[s2 + 1] - st.isub_ptr[s2]) *
+                                        (st.sub_ptr[s2 + 1] - st.sub_ptr[s2]);
+  // boundary weights -B_s psi_n: entry k collects -2 a_e over the edges of E_n at k
+  std::vector<int32_t> e_kloc(d.NE), e_lloc(d.NE);
+  std::vector<std::vector<std::pair<int32_t, double>>> wts(npair);
+  for (int64_t nidx = 0; nidx < NL; ++nidx) {
+    const int32_t i = st.iface_ij[2 * nidx], j = st.iface_ij[2 * nidx + 1];
+    for (int64_t e2 = st.iface_ptr[nidx]; e2 < st.iface_ptr[nidx + 1]; ++e2) {
+      const int32_t kl = dpos[st.edge_k[e2]] - (int32_t)st.sub_ptr[i];
+      const int32_t ll = dpos[st.edge_l[e2]] - (int32_t)st.sub_ptr[j];
+      e_kloc[e2] = kl;
+      e_lloc[e2] = ll;
+      wts[bidx[2 * nidx]].emplace_back(kl, -2.0 * st.edge_a[e2]);
+      wts[bidx[2 * nidx + 1]].emplace_back(ll, -2.0 * st.edge_a[e2]);
+    }
+  }
+  std::vector<int64_t> bw_ptr(npair + 1, 0);
+  std::vector<int32_t> bw_row;
+  std::vector<double> bw_val;
+  for (int64_t pi = 0; pi < npair; ++pi) {
+    auto& v = wts[pi];
+    std::stable_sort(v.begin(), v.end(),
+                     [](const std::pair<int32_t, double>& a, const std::pair<int32_t, double>& b) {
+                       return a.first < b.first;
+                     });
+    for (size_t t = 0; t < v.size(); ++t) {
+      if (t > 0 && v[t].first == v[t - 1].first)
+        bw_val.back() += v[t].second;
+      else {
+        bw_row.push_back(v[t].first);
+        bw_val.push_back(v[t].second);
+      }
+    }
+    bw_ptr[pi + 1] = (int64_t)bw_row.size();
+    std::vector<std::pair<int32_t, double>>().swap(v);
+  }
+
+  // ---- device upload ----
+  std::vector<void*>& al = d.allocs;
+  SCHK(upload(al, &d.dperm, dperm, sm));
+  SCHK(upload(al, &d.ell_col, ell_col, sm));
+  SCHK(upload(al, &d.ell_val, ell_val, sm));
+  SCHK(upload(al, &d.prp, prp, sm));
+  SCHK(upload(al, &d.pci, pci, sm));
+  SCHK(upload(al, &d.pv, pv, sm));
+  SCHK(upload(al, &d.sub_ptr, st.sub_ptr, sm));
+  SCHK(upload(al, &d.wp, lp.wp, sm));
+  SCHK(upload(al, &d.roff, lp.roff, sm));
+  SCHK(upload(al, &d.fac_off, lp.fac_off, sm));
+  for (int bk = 0; bk < 2; ++bk) {
+    SCHK(upload(al, &d.d_bucket_sub[bk], d.bucket_sub[bk], sm));
+    SCHK(upload(al, &d.d_bucket_pair[bk], d.bucket_pair[bk], sm));
+  }
+  SCHK(upload(al, &d.isub_ptr, st.isub_ptr, sm));
+  SCHK(upload(al, &d.isub_list, st.isub_list, sm));
+  SCHK(upload(al, &d.mbf_off, mbf_off, sm));
+  SCHK(upload(al, &d.bw_ptr, bw_ptr, sm));
+  SCHK(upload(al, &d.bw_row, bw_row, sm));
+  SCHK(upload(al, &d.bw_val, bw_val, sm));
+  SCHK(upload(al, &d.mbf_pair_sub, pair_sub, sm));
+  SCHK(upload(al, &d.mbf_pair_q, pair_q, sm));
+  SCHK(upload(al, &d.iface_ptr, st.iface_ptr, sm));
+  SCHK(upload(al, &d.iface_ij, st.iface_ij, sm));
+  SCHK(upload(al, &d.e_kloc, e_kloc, sm));
+  SCHK(upload(al, &d.e_lloc, e_lloc, sm));
+  SCHK(upload(al, &d.e_a, st.edge_a, sm));
+  SCHK(upload(al, &d.bidx, bidx, sm));
+  std::vector<double>().swap(ell_val);
+  std::vector<int32_t>().swap(ell_col);
+
+  const size_t esz = d.prec == AM_FP64 ? 8 : (d.prec == AM_FP32 ? 4 : 2);
+  const size_t isz = d.prec == AM_FP64 ? 8 : 4;
+  const size_t nfac = (size_t)lp.fac_off[st.m];
+  uint8_t *Lc = nullptr, *Lr = nullptr, *iv = nullptr;
+  SCHK(dalloc(al, &Lc, nfac * esz));
+  SCHK(dalloc(al, &Lr, nfac * esz));
+  SCHK(dalloc(al, &iv, (size_t)lp.roff[st.m] * isz));
+  d.Lc = Lc;
+  d.Lr = Lr;
+  d.invd = iv;
+  SCHK(hipMemsetAsync(Lc, 0, nfac * esz, sm));
+  SCHK(hipMemsetAsync(Lr, 0, nfac * esz, sm));
+  SCHK(dalloc(al, &d.fail, 4));
+  SCHK(hipMemsetAsync(d.fail, 0xFF, 4 * sizeof(int32_t), sm));
+  SCHK(dalloc(al, &d.mbf, (size_t)mbf_off[st.m]));
+  const size_t nS = (size_t)d.ldS * d.ldS;
+  SCHK(dalloc(al, &d.S, nS));
+  SCHK(dalloc(al, &d.Sinv, nS));
+
+  const int NRm = d.max_nrhs;
+  const size_t nv = (size_t)n * NRm;
+  SCHK(dalloc(al, &d.x, nv));
+  SCHK(dalloc(al, &d.r, nv));
+  SCHK(dalloc(al, &d.z, nv));
+  SCHK(dalloc(al, &d.p[0], nv));
+  SCHK(dalloc(al, &d.p[1], nv));
+  SCHK(dalloc(al, &d.q, nv));
+  SCHK(dalloc(al, &h->bp, nv));
+  SCHK(dalloc(al, &d.bpart, (size_t)std::max<int64_t>(npair, 1) * NRm));
+  SCHK(dalloc(al, &d.eta, (size_t)std::max<int32_t>(d.ldS, 1) * NRm));
+  SCHK(dalloc(al, &d.sc, kMaxNRHS));
+  SCHK(dalloc(al, &d.shared, 1));
+  SCHK(dalloc(al, &h->tres, kMaxNRHS));
+  d.red.max_blocks = (int)std::max<int64_t>((n + 255) / 256, st.m) + 1;
+  SCHK(dalloc(al, &d.red.partial, (size_t)d.red.max_blocks * 2 * kMaxNRHS));
+  SCHK(dalloc(al, &d.red.counter, 8));
+  SCHK(hipMemsetAsync(d.red.counter, 0, 8 * sizeof(unsigned), sm));
+  SCHK(hipMemsetAsync(d.shared, 0, sizeof(PcgShared), sm));
+  SCHK(hipHostMalloc((void**)&d.h_flags, 4 * sizeof(int32_t), hipHostMallocDefault));
+
+  // ---- Algorithm 1 on the device ----
+  SCHK(launch_band_factor(d, sm));
+  SCHK(launch_mbf(d, sm));
+  SCHK(launch_assemble_S(d, sm));
+  if (NL > 0) {
+    double *L = nullptr, *Li = nullptr;
+    SCHK(hipMalloc((void**)&L, nS * sizeof(double)));
+    hipError_t he = hipMalloc((void**)&Li, nS * sizeof(double));
+    if (he != hipSuccess) {
+      hipFree(L);
+      return hipfail(he, "hipMalloc(L^-1)");
+    }
+    he = dense_cholesky_inverse(d, L, Li, sm);
+    hipError_t he2 = hipStreamSynchronize(sm);
+    hipFree(L);
+    hipFree(Li);
+    if (he != hipSuccess) return hipfail(he, "dense_cholesky_inverse");
+    if (he2 != hipSuccess) return hipfail(he2, "interface factorization");
+  }
+  SCHK(hipStreamSynchronize(sm));
+  int32_t fl[4];
+  SCHK(hipMemcpy(fl, d.fail, sizeof(fl), hipMemcpyDeviceToHost));
+  if (fl[0] >= 0) {
+    fail(h, AM_ERR_NOT_SPD, "A_i not SPD: subdomain " + std::to_string(fl[0]) + " pivot " +
+                                std::to_string(fl[1]));
+    return bail(AM_ERR_NOT_SPD);
+  }
+  if (fl[2] >= 0) {
+    fail(h, AM_ERR_NOT_SPD, "interface matrix S not SPD at row " + std::to_string(fl[2]));
+    return bail(AM_ERR_NOT_SPD);
+  }
+  // free set-up only arrays
+  *out = h;
+  return AM_OK;
+#undef SCHK
+}
+
+// ---------------------------------------------------------------------------
+static am_status check_vec_args(am_handle h, const void* a, const void* b, int32_t nrhs,
+                                int64_t ld) {
+  if (!h) return fail(nullptr, AM_ERR_ARG, "null handle");
+  if (!a || !b) return fail(h, AM_ERR_ARG, "null vector");
+  if (nrhs < 1 || pow2_at_least(nrhs) > h->d.max_nrhs)
+    return fail(h, AM_ERR_ARG, "nrhs out of range (max_nrhs at set-up)");
+  if (nrhs > 1 && ld < h->d.n) return fail(h, AM_ERR_ARG, "ld < n");
+  return AM_OK;
+}
+
+am_status algmortar_apply(am_handle h, const double* r, double* z, int32_t nrhs, int64_t ld,
+                          void* stream) {
+  am_status s = check_vec_args(h, r, z, nrhs, ld);
+  if (s != AM_OK) return s;
+  if (nrhs == 1) ld = h->d.n;
+  DeviceState& d = h->d;
+  HCHK(hipSetDevice(d.device));
+  hipStream_t st = (hipStream_t)stream;
+  const int nr = pow2_at_least(nrhs);
+  HCHK(launch_permute_in(d.dperm, d.n, r, ld, d.r, nrhs, st));
+  if (d.NL > 0) {
+    HCHK(launch_bpart(d, d.r, nr, st));
+    HCHK(launch_iface_gemv(d, nr, st));
+  }
+  HCHK(launch_local_sweep(d, d.r, d.z, d.eta, nr, 1, st));
+  HCHK(launch_permute_out(d.dperm, d.n, d.z, z, ld, nrhs, st));
+  return AM_OK;
+}
+
+am_status algmortar_local_solve(am_handle h, const double* r, double* pbar, void* stream) {
+  am_status s = check_vec_args(h, r, pbar, 1, 0);
+  if (s != AM_OK) return s;
+  DeviceState& d = h->d;
+  HCHK(hipSetDevice(d.device));
+  hipStream_t st = (hipStream_t)stream;
+  HCHK(launch_permute_in(d.dperm, d.n, r, d.n, d.r, 1, st));
+  HCHK(launch_local_sweep(d, d.r, d.z, d.eta, 1, 0, st));
+  HCHK(launch_permute_out(d.dperm, d.n, d.z, pbar, d.n, 1, st));
+  return AM_OK;
+}
+
+static constexpr int kChunk = 8;  // iterations per captured graph (even: p ping-pong)
+
+static hipError_t run_chunk(DeviceState& d, int nr, hipStream_t st) {
+  for (int it = 0; it < kChunk; ++it) {
+    hipError_t e = launch_pcg_iteration(d, nr, it & 1, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+am_status algmortar_pcg(am_handle h, const double* b, double* x, int32_t nrhs, int64_t ld,
+                        double tol, int32_t maxit, am_info* info, void* stream) {
+  am_status s = check_vec_args(h, b, x, nrhs, ld);
+  if (s != AM_OK) return s;
+  if (!(tol > 0.0) || !(tol < 1.0)) return fail(h, AM_ERR_ARG, "tol must be in (0, 1)");
+  if (maxit <= 0) maxit = 10000;
+  if (nrhs == 1) ld = h->d.n;
+  DeviceState& d = h->d;
+  HCHK(hipSetDevice(d.device));
+  if (stream) HCHK(hipStreamSynchronize((hipStream_t)stream));
+  hipStream_t st = h->own;
+  const int nr = pow2_at_least(nrhs);
+  const int64_t nv = d.n * nr;
+  HCHK(hipEventRecord(h->ev0, st));
+  HCHK(launch_permute_in(d.dperm, d.n, b, ld, d.r, nrhs, st));
+  HCHK(launch_permute_in(d.dperm, d.n, b, ld, h->bp, nrhs, st));
+  HCHK(launch_fill(d.x, nv, 0.0, st));
+  HCHK(launch_fill(d.z, nv, 0.0, st));
+  HCHK(launch_fill(d.q, nv, 0.0, st));
+  HCHK(launch_fill(d.p[0], nv, 0.0, st));
+  HCHK(launch_fill(d.p[1], nv, 0.0, st));
+  HCHK(launch_fill(d.eta, (int64_t)std::max<int32_t>(d.ldS, 1) * nr, 0.0, st));
+  HCHK(launch_pcg_init(d, nr, tol, maxit, d.prec != AM_FP64 ? 1 : 0, st));
+  HCHK(launch_pcg_start(d, nr, st));
+  const bool use_graph = !(h->opt.flags & AM_FLAG_NO_GRAPH);
+  if (use_graph && (d.graph == nullptr || d.graph_nrhs != nr)) {
+    if (d.graph) {
+      HCHK(hipGraphExecDestroy(d.graph));
+      d.graph = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    HCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    hipError_t ce = run_chunk(d, nr, st);
+    hipError_t ee = hipStreamEndCapture(st, &g);
+    if (ce != hipSuccess) return fail(h, AM_ERR_HIP, std::string("capture: ") + hipGetErrorString(ce));
+    if (ee != hipSuccess) return fail(h, AM_ERR_HIP, std::string("end capture: ") + hipGetErrorString(ee));
+    hipError_t ie = hipGraphInstantiate(&d.graph, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (ie != hipSuccess) {
+      d.graph = nullptr;
+      return fail(h, AM_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(ie));
+    }
+    d.graph_nrhs = nr;
+  }
+  const int max_chunks = maxit / kChunk + 2;
+  for (int c = 0; c < max_chunks; ++c) {
+    if (use_graph)
+      HCHK(hipGraphLaunch(d.graph, st));
+    else
+      HCHK(run_chunk(d, nr, st));
+    HCHK(hipMemcpyAsync(d.h_flags, &d.shared->all_done, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HCHK(hipStreamSynchronize(st));
+    if (d.h_flags[0]) break;
+  }
+  HCHK(launch_permute_out(d.dperm, d.n, d.x, x, ld, nrhs, st));
+  HCHK(hipEventRecord(h->ev1, st));
+  HCHK(launch_true_residual(d, h->bp, nr, h->tres, st));
+  PcgScalars sc[kMaxNRHS];
+  double tr[kMaxNRHS];
+  HCHK(hipMemcpyAsync(sc, d.sc, sizeof(PcgScalars) * nr, hipMemcpyDeviceToHost, st));
+  HCHK(hipMemcpyAsync(tr, h->tres, sizeof(double) * nr, hipMemcpyDeviceToHost, st));
+  HCHK(hipStreamSynchronize(st));
+  float ms = 0.f;
+  HCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+  am_status ret = AM_OK;
+  for (int k = 0; k < nrhs; ++k) {
+    const double bb = sc[k].bb;
+    if (info) {
+      info[k].iterations = sc[k].it;
+      info[k].converged = sc[k].conv;
+      info[k].rel_res = bb > 0 ? std::sqrt(sc[k].rr / bb) : 0.0;
+      info[k].true_rel_res = bb > 0 ? std::sqrt(tr[k] / bb) : 0.0;
+      info[k].solve_ms = ms;
+    }
+    if (!sc[k].done && ret == AM_OK) ret = AM_ERR_NO_CONVERGENCE;
+    if (sc[k].status == AM_ERR_BREAKDOWN) ret = AM_ERR_BREAKDOWN;
+    else if (sc[k].status == AM_ERR_NO_CONVERGENCE && ret == AM_OK) ret = AM_ERR_NO_CONVERGENCE;
+  }
+  if (ret == AM_ERR_BREAKDOWN) return fail(h, ret, "PCG breakdown: nonpositive curvature");
+  if (ret == AM_ERR_NO_CONVERGENCE) return fail(h, ret, "PCG did not converge within maxit");
+  return AM_OK;
+}
+
+am_status algmortar_interfaces(am_handle h, int32_t* perm, int64_t* sub_ptr, int64_t* iface_ptr,
+                               int32_t* iface_ij, int32_t* edge_k, int32_t* edge_l) {
+  if (!h) return fail(nullptr, AM_ERR_ARG, "null handle");
+  copy_structure(h->st, perm, sub_ptr, iface_ptr, iface_ij, edge_k, edge_l);
+  return AM_OK;
+}
+
+am_status algmortar_sizes(am_handle h, int64_t* n, int64_t* nparts, int64_t* n_iface,
+                          int64_t* n_edges) {
+  if (!h) return fail(nullptr, AM_ERR_ARG, "null handle");
+  if (n) *n = h->d.n;
+  if (nparts) *nparts = h->d.m;
+  if (n_iface) *n_iface = h->d.NL;
+  if (n_edges) *n_edges = h->d.NE;
+  return AM_OK;
+}
+
+am_status algmortar_export_interface(am_handle h, int32_t which, double* out) {
+  if (!h || !out || (which != 0 && which != 1)) return fail(h, AM_ERR_ARG, "bad argument");
+  DeviceState& d = h->d;
+  if (d.NL == 0) return AM_OK;
+  HCHK(hipSetDevice(d.device));
+  const double* src = which == 0 ? d.S : d.Sinv;
+  HCHK(hipMemcpy2D(out, sizeof(double) * d.NL, src, sizeof(double) * d.ldS, sizeof(double) * d.NL,
+                   d.NL, hipMemcpyDeviceToHost));
+  return AM_OK;
+}
+
+am_status algmortar_export_mbf(am_handle h, int64_t iface, int32_t sub, double* out) {
+  if (!h || !out || iface < 0 || iface >= h->d.NL) return fail(h, AM_ERR_ARG, "bad argument");
+  const Structure& st = h->st;
+  if (st.iface_ij[2 * iface] != sub && st.iface_ij[2 * iface + 1] != sub)
+    return fail(h, AM_ERR_ARG, "subdomain is not a side of the interface");
+  int64_t q = -1;
+  for (int64_t pi = st.isub_ptr[sub]; pi < st.isub_ptr[sub + 1]; ++pi)
+    if (st.isub_list[pi] == iface) q = pi - st.isub_ptr[sub];
+  int64_t off = 0;
+  for (int32_t s2 = 0; s2 < sub; ++s2)
+    off += (st.isub_ptr[s2 + 1] - st.isub_ptr[s2]) * (st.sub_ptr[s2 + 1] - st.sub_ptr[s2]);
+  const int64_t N = st.sub_ptr[sub + 1] - st.sub_ptr[sub];
+  std::vector<double> tmp((size_t)N);
+  HCHK(hipSetDevice(h->d.device));
+  HCHK(hipMemcpy(tmp.data(), h->d.mbf + off + q * N, sizeof(double) * N, hipMemcpyDeviceToHost));
+  for (int64_t r = 0; r < N; ++r) {
+    const int32_t o = st.perm[st.sub_ptr[sub] + r];
+    out[r] = tmp[h->lp.dpos[o] - st.sub_ptr[sub]];
+  }
+  return AM_OK;
+}
+
+am_status algmortar_time_kernel(am_handle h, int32_t kernel, int32_t nrhs, int32_t reps,
+                                double* avg_ms, double* bytes) {
+  if (!h || !avg_ms || !bytes || reps < 1 || kernel < 0 || kernel > 2 || nrhs < 1 ||
+      pow2_at_least(nrhs) > h->d.max_nrhs)
+    return fail(h, AM_ERR_ARG, "bad argument");
+  DeviceState& d = h->d;
+  const Structure& st = h->st;
+  const LocalPlan& lp = h->lp;
+  const int nr = pow2_at_least(nrhs);
+  const double esz = d.prec == AM_FP64 ? 8 : (d.prec == AM_FP32 ? 4 : 2);
+  const double isz = d.prec == AM_FP64 ? 8 : 4;
+  double by = 0.0;
+  if (kernel == 0) {
+    for (int32_t s2 = 0; s2 < st.m; ++s2) {
+      const double N = (double)(st.sub_ptr[s2 + 1] - st.sub_ptr[s2]);
+      const double NP = (double)(lp.roff[s2 + 1] - lp.roff[s2]);
+      const double ns = (double)(st.isub_ptr[s2 + 1] - st.isub_ptr[s2]);
+      by += 2.0 * NP * lp.wp[s2] * esz + 2.0 * NP * isz + 2.0 * N * 8.0 * nr + ns * N * 8.0;
+    }
+    by += (double)d.NL * 8.0 * nr;
+  } else if (kernel == 1) {
+    by = (double)d.NL * d.NL * 8.0 + 3.0 * d.NL * 8.0 * nr;
+  } else {
+    for (int32_t s2 = 0; s2 < st.m; ++s2) {
+      const double N = (double)(st.sub_ptr[s2 + 1] - st.sub_ptr[s2]);
+      const double ns = (double)(st.isub_ptr[s2 + 1] - st.isub_ptr[s2]);
+      by += ns * N * 8.0 + N * 8.0 * nr;
+    }
+    by += 2.0 * d.NL * 8.0 * nr;
+  }
+  HCHK(hipSetDevice(d.device));
+  hipStream_t st0 = h->own;
+  auto launch = [&]() -> hipError_t {
+    if (kernel == 0) return launch_local_sweep(d, d.r, d.z, d.eta, nr, 1, st0);
+    if (kernel == 1) return launch_iface_gemv(d, nr, st0);
+    return launch_bpart(d, d.r, nr, st0);
+  };
+  HCHK(launch());  // warm-up
+  HCHK(hipEventRecord(h->ev0, st0));
+  for (int i = 0; i < reps; ++i) HCHK(launch());
+  HCHK(hipEventRecord(h->ev1, st0));
+  HCHK(hipEventSynchronize(h->ev1));
+  float ms = 0.f;
+  HCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+  *avg_ms = ms / reps;
+  *bytes = by;
+  return AM_OK;
+}
+
+// ---------------------------------------------------------------------------
+am_status am_tpfa_create(const am_faces* f, int64_t n, int32_t device, am_tpfa* out,
+                         int64_t* nnz) {
+  if (!f || !out || n <= 0 || f->n_faces < 0 || (f->n_faces > 0 && (!f->k || !f->l || !f->gk || !f->gl || !f->pD)))
+    return fail(nullptr, AM_ERR_ARG, "bad face list");
+  *out = nullptr;
+  const int64_t nf = f->n_faces;
+  for (int64_t i = 0; i < nf; ++i) {
+    if (f->k[i] < 0 || f->k[i] >= n || f->l[i] < -1 || f->l[i] >= n || f->l[i] == f->k[i])
+      return fail(nullptr, AM_ERR_ARG, "face " + std::to_string(i) + " has a bad cell index");
+    if (!(f->gk[i] > 0) || (f->l[i] >= 0 && !(f->gl[i] > 0)))
+      return fail(nullptr, AM_ERR_ARG, "face " + std::to_string(i) + " has a nonpositive factor");
+  }
+  am_tpfa t = new am_tpfa_s();
+  TpfaDevice& T = t->t;
+  T.device = device;
+  T.n = n;
+  T.nf = nf;
+  // pattern: diagonal + the other cell of every interior face, columns ascending
+  std::vector<std::vector<int64_t>> cols((size_t)n);
+  for (int64_t c = 0; c < n; ++c) cols[c].push_back(c);
+  for (int64_t i = 0; i < nf; ++i)
+    if (f->l[i] >= 0) {
+      cols[f->k[i]].push_back(f->l[i]);
+      cols[f->l[i]].push_back(f->k[i]);
+    }
+  T.h_rp.assign(n + 1, 0);
+  for (int64_t c = 0; c < n; ++c) {
+    std::sort(cols[c].begin(), cols[c].end());
+    if (std::adjacent_find(cols[c].begin(), cols[c].end()) != cols[c].end()) {
+      delete t;
+      return fail(nullptr, AM_ERR_ARG, "two faces join the same pair of cells");
+    }
+    T.h_rp[c + 1] = T.h_rp[c] + (int64_t)cols[c].size();
+  }
+  T.nnz = T.h_rp[n];
+  T.h_ci.resize((size_t)T.nnz);
+  for (int64_t c = 0; c < n; ++c)
+    for (size_t q = 0; q < cols[c].size(); ++q) T.h_ci[T.h_rp[c] + q] = (int32_t)cols[c][q];
+  auto slot = [&](int64_t r, int64_t c) {
+    const int32_t* b = T.h_ci.data() + T.h_rp[r];
+    const int32_t* e = T.h_ci.data() + T.h_rp[r + 1];
+    return T.h_rp[r] + (std::lower_bound(b, e, (int32_t)c) - b);
+  };
+  std::vector<int64_t> skk(n), skl(nf, 0), slk(nf, 0), cf_ptr(n + 1, 0);
+  for (int64_t c = 0; c < n; ++c) skk[c] = slot(c, c);
+  for (int64_t i = 0; i < nf; ++i) {
+    cf_ptr[f->k[i] + 1]++;
+    if (f->l[i] >= 0) {
+      skl[i] = slot(f->k[i], f->l[i]);
+      slk[i] = slot(f->l[i], f->k[i]);
+      cf_ptr[f->l[i] + 1]++;
+    }
+  }
+  for (int64_t c = 0; c < n; ++c) cf_ptr[c + 1] += cf_ptr[c];
+  std::vector<int32_t> cf_face(cf_ptr[n]);
+  {
+    std::vector<int64_t> fill(cf_ptr.begin(), cf_ptr.end() - 1);
+    for (int64_t i = 0; i < nf; ++i) {
+      cf_face[fill[f->k[i]]++] = (int32_t)i;
+      if (f->l[i] >= 0) cf_face[fill[f->l[i]]++] = (int32_t)i;
+    }
+  }
+  am_handle h = nullptr;
+  auto bail = [&](hipError_t e, const char* what) {
+    std::string msg = std::string(what) + ": " + hipGetErrorString(e);
+    am_tpfa_destroy(t);
+    return fail(nullptr, e == hipErrorOutOfMemory ? AM_ERR_OOM : AM_ERR_HIP, msg);
+  };
+  hipError_t e = hipSetDevice(device);
+  if (e != hipSuccess) return bail(e, "hipSetDevice");
+  std::vector<int64_t> fk(f->k, f->k + nf), fl(f->l, f->l + nf);
+  std::vector<double> gk(f->gk, f->gk + nf), gl(f->gl, f->gl + nf), pD(f->pD, f->pD + nf);
+  hipStream_t s0 = nullptr;
+#define TUP(p, v)                         \
+  do {                                    \
+    e = upload(T.allocs, &p, v, s0);      \
+    if (e != hipSuccess) return bail(e, #p); \
+  } while (0)
+  TUP(T.fk, fk);
+  TUP(T.fl, fl);
+  TUP(T.gk, gk);
+  TUP(T.gl, gl);
+  TUP(T.pD, pD);
+  TUP(T.slot_kk, skk);
+  TUP(T.slot_kl, skl);
+  TUP(T.slot_lk, slk);
+  TUP(T.cf_ptr, cf_ptr);
+  TUP(T.cf_face, cf_face);
+#undef TUP
+  (void)h;
+  if (nnz) *nnz = T.nnz;
+  *out = t;
+  return AM_OK;
+}
+
+am_status am_tpfa_pattern(am_tpfa t, int64_t* row_ptr, int32_t* col_idx) {
+  if (!t) return fail(nullptr, AM_ERR_ARG, "null tpfa handle");
+  if (row_ptr) std::copy(t->t.h_rp.begin(), t->t.h_rp.end(), row_ptr);
+  if (col_idx) std::copy(t->t.h_ci.begin(), t->t.h_ci.end(), col_idx);
+  return AM_OK;
+}
+
+am_status am_tpfa_assemble(am_tpfa t, const double* logK, double* val, double* f, void* stream) {
+  if (!t || !logK || !val) return fail(nullptr, AM_ERR_ARG, "bad argument");
+  am_handle h = nullptr;
+  HCHK(hipSetDevice(t->t.device));
+  HCHK(launch_tpfa_assemble(t->t, logK, val, f, (hipStream_t)stream));
+  return AM_OK;
+}
+
+am_status am_tpfa_face_grad(am_tpfa t, const double* logK, const double* p, const double* lambda,
+                            double* grad, void* stream) {
+  if (!t || !logK || !p || !lambda || !grad) return fail(nullptr, AM_ERR_ARG, "bad argument");
+  am_handle h = nullptr;
+  HCHK(hipSetDevice(t->t.device));
+  HCHK(launch_face_grad(t->t, logK, p, lambda, grad, (hipStream_t)stream));
+  return AM_OK;
+}
+
+am_status am_tpfa_destroy(am_tpfa t) {
+  if (!t) return AM_OK;
+  hipSetDevice(t->t.device);
+  for (void* p : t->t.allocs) hipFree(p);
+  delete t;
+  return AM_OK;
+}
+
+am_status algmortar_adjoint_grad(am_handle h, am_tpfa t, const double* logK, const double* p,
+                                 const double* dJdp, double tol, int32_t maxit, double* lambda,
+                                 double* grad, am_info* info, void* stream) {
+  if (!h || !t || !logK || !p || !dJdp || !lambda || !grad)
+    return fail(h, AM_ERR_ARG, "bad argument");
+  if (t->t.n != h->d.n) return fail(h, AM_ERR_ARG, "face list and handle sizes differ");
+  am_status s = algmortar_pcg(h, dJdp, lambda, 1, h->d.n, tol, maxit, info, stream);
+  if (s != AM_OK) return s;
+  HCHK(launch_face_grad(t->t, logK, p, lambda, grad, h->own));
+  HCHK(hipStreamSynchronize(h->own));
+  return AM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,136 @@
+// Small device helpers shared by the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "am_device.h"
+
+namespace am {
+
+typedef uint16_t bf16_t;
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  int2 b = __builtin_bit_cast(int2, v);
+  b.x = __builtin_amdgcn_readlane(b.x, lane);
+  b.y = __builtin_amdgcn_readlane(b.y, lane);
+  return __builtin_bit_cast(double, b);
+}
+__device__ __forceinline__ float readlane_f(float v, int lane) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
+__device__ __forceinline__ double readlane(double v, int lane) { return readlane_d(v, lane); }
+__device__ __forceinline__ float readlane(float v, int lane) { return readlane_f(v, lane); }
+
+// factor element loads (bf16 is stored as raw bits, widened to fp32)
+__device__ __forceinline__ double ld_fac(const double* p) { return *p; }
+__device__ __forceinline__ float ld_fac(const float* p) { return *p; }
+__device__ __forceinline__ float ld_fac(const bf16_t* p) {
+  return __builtin_bit_cast(float, ((uint32_t)*p) << 16);
+}
+// round-to-nearest-even conversions from fp64
+__device__ __forceinline__ void st_fac(double* p, double v) { *p = v; }
+__device__ __forceinline__ void st_fac(float* p, double v) { *p = (float)v; }
+__device__ __forceinline__ void st_fac(bf16_t* p, double v) {
+  float f = (float)v;
+  uint32_t u = __builtin_bit_cast(uint32_t, f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  *p = (bf16_t)(u >> 16);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum of v[k] over the block (fixed tree); result valid in every thread.
+// lds must hold (blockDim.x/64) * NR doubles.
+template <int NR>
+__device__ __forceinline__ void block_sum(double (&v)[NR], double* lds) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NR; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < NR; ++k) lds[w * NR + k] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    double s = 0.0;
+    for (int i = 0; i < nw; ++i) s += lds[i * NR + k];
+    v[k] = s;
+  }
+  __syncthreads();
+}
+
+// Publish this block's sums and tell whether it is the last block of the
+// launch to do so.  The last block then reads every block's partial sums (in
+// block order, so the total is deterministic) and resets the counter.
+template <int NR>
+__device__ __forceinline__ bool publish_partial(const double (&v)[NR], double* partial,
+                                                unsigned* counter, unsigned nblocks) {
+  __shared__ int last;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NR; ++k) partial[(size_t)blockIdx.x * NR + k] = v[k];
+    __threadfence();
+    unsigned prev = atomicAdd(counter, 1u);
+    last = (prev == nblocks - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (last) __threadfence();
+  return last != 0;
+}
+
+template <int NR>
+__device__ __forceinline__ void reduce_partials(double (&tot)[NR], const double* partial,
+                                                unsigned nblocks, double* lds) {
+#pragma unroll
+  for (int k = 0; k < NR; ++k) tot[k] = 0.0;
+  for (unsigned b = threadIdx.x; b < nblocks; b += blockDim.x)
+#pragma unroll
+    for (int k = 0; k < NR; ++k) tot[k] += partial[(size_t)b * NR + k];
+  block_sum<NR>(tot, lds);
+}
+
+__device__ __forceinline__ bool all_done(const PcgShared* sh) {
+  return *(volatile const int32_t*)&sh->all_done != 0;
+}
+
+// ---------------------------------------------------------------------------
+// Interface partial right-hand sides from r (not from pbar): for subdomain s
+// and slot q (basis function n = I_s[q]),
+//   bpart[s,q] = 1/4 * phat^(n)_s . r_s,
+// so that b_n = bpart[i, q_i] + bpart[j, q_j] = -sum_{e in E_n} a_e (pbar_k + pbar_l)/2.
+// (A_s is symmetric and phat^(n)_s = A_s^{-1}(-B_s psi_n) = 4 A_s^{-1} w with
+// w_k = -sum a_e / 2 the weights of the edge average.)
+template <int NR>
+__device__ __forceinline__ void bpart_sub(int s, const int64_t* __restrict__ sub_ptr,
+                                          const int64_t* __restrict__ isub_ptr,
+                                          const int64_t* __restrict__ mbf_off,
+                                          const double* __restrict__ mbf, const double* r,
+                                          double* bpart, double* lds) {
+  const int64_t base = sub_ptr[s];
+  const int N = (int)(sub_ptr[s + 1] - base);
+  const int64_t i0 = isub_ptr[s];
+  const int ns = (int)(isub_ptr[s + 1] - i0);
+  const double* P = mbf + mbf_off[s];
+  for (int q = 0; q < ns; ++q) {
+    double v[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) v[k] = 0.0;
+    for (int row = threadIdx.x; row < N; row += blockDim.x) {
+      const double ph = P[(size_t)q * N + row];
+#pragma unroll
+      for (int k = 0; k < NR; ++k) v[k] = fma(ph, r[(size_t)(base + row) * NR + k], v[k]);
+    }
+    block_sum<NR>(v, lds);
+    if (threadIdx.x == 0)
+#pragma unroll
+      for (int k = 0; k < NR; ++k) bpart[(size_t)(i0 + q) * NR + k] = 0.25 * v[k];
+  }
+}
+
+}  // namespace am

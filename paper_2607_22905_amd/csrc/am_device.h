@@ -1,0 +1,172 @@
+// Device-side state of an AlgMortar handle and the launchers of the gfx950
+// kernels.  Internal header (not part of the C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "am_host.h"
+
+namespace am {
+
+constexpr int kMaxNRHS = 16;
+constexpr int kMaxWp = 128;   // widest band window the LDS factor kernel holds
+constexpr int kTile = 64;     // dense interface-matrix tile
+
+// PCG scalars of one right-hand side, device resident.
+struct PcgScalars {
+  double rz;      // (r, z) of the current iterate
+  double pq;      // (p, A p)
+  double alpha;
+  double beta;
+  double rr;      // ||r||^2
+  double bb;      // ||b||^2
+  double tol2;    // tol^2
+  double qz;      // (q, z_new), for the flexible beta
+  int32_t it;     // iterations done
+  int32_t done;   // 1 once converged / stopped
+  int32_t status; // am_status of this column
+  int32_t conv;   // 1 if converged
+};
+
+struct PcgShared {
+  int32_t maxit;
+  int32_t nrhs;
+  int32_t flexible;  // Polak-Ribiere beta
+  int32_t all_done;
+};
+
+// Scalar partial sums written by the reducing kernels; reduced by the last
+// workgroup of each launch in a fixed order (deterministic).
+struct Reduce {
+  double* partial = nullptr;    // [max_blocks * kMaxNRHS * 2]
+  unsigned* counter = nullptr;  // one counter per reducing kernel kind
+  int max_blocks = 0;
+};
+
+struct DeviceState {
+  int device = 0;
+  int prec = AM_FP64;
+  int64_t n = 0;
+  int32_t m = 0;
+  int64_t NL = 0, NE = 0;
+  int32_t ldS = 0;  // padded interface dimension (multiple of kTile)
+  int32_t max_nrhs = 1;
+
+  // device ordering and permuted matrix
+  int32_t* dperm = nullptr;    // [n] device position -> original index
+  int32_t ell_w = 0;
+  int32_t* ell_col = nullptr;  // [ell_w * n] column-major, device positions
+  double* ell_val = nullptr;
+  int64_t* prp = nullptr;      // permuted CSR (rows/cols in device positions)
+  int32_t* pci = nullptr;
+  double* pv = nullptr;
+
+  // subdomains
+  int64_t* sub_ptr = nullptr;  // [m+1]
+  int32_t* wp = nullptr;       // [m]
+  int64_t* roff = nullptr;     // [m+1] padded row offsets of the factor blocks
+  int64_t* fac_off = nullptr;  // [m+1] element offsets of the factor blocks
+  void* Lc = nullptr;          // band factor, column layout (precision dependent)
+  void* Lr = nullptr;          // band factor, row layout
+  void* invd = nullptr;        // [n] 1/L_jj (double for FP64, float otherwise)
+  std::vector<int32_t> bucket_sub[2];  // host: subdomain ids per window width 64/128
+  int32_t* d_bucket_sub[2] = {nullptr, nullptr};
+  std::vector<int32_t> bucket_pair[2]; // host: (subdomain, slot) pairs per window width
+  int32_t* d_bucket_pair[2] = {nullptr, nullptr};
+  int32_t* fail = nullptr;     // [4]: failing subdomain and pivot of A_i; failing row of S (device)
+
+  // mortar structure
+  int64_t* isub_ptr = nullptr;   // [m+1]
+  int32_t* isub_list = nullptr;  // [2 NL]
+  int64_t* mbf_off = nullptr;    // [m+1] offsets of P^_s blocks ([n_s][N_s])
+  double* mbf = nullptr;
+  int64_t* bw_ptr = nullptr;     // [2 NL + 1] boundary weights per (subdomain, slot)
+  int32_t* bw_row = nullptr;     // local row (device order inside the subdomain)
+  double* bw_val = nullptr;      // -2 * sum a_e  (= -B_s psi_n)
+  int32_t* mbf_pair_sub = nullptr;  // [2 NL] subdomain of each (s, slot) pair
+  int32_t* mbf_pair_q = nullptr;    // [2 NL] slot
+  int64_t* iface_ptr = nullptr;  // [NL+1]
+  int32_t* iface_ij = nullptr;   // [2 NL]
+  int32_t* e_kloc = nullptr;     // [NE] local row of k in subdomain i
+  int32_t* e_lloc = nullptr;     // [NE] local row of l in subdomain j
+  double* e_a = nullptr;         // [NE]
+  int64_t* bidx = nullptr;       // [2 NL] index into the (subdomain, slot) partials
+  double* S = nullptr;           // [ldS * ldS] symmetrised interface matrix
+  double* Sinv = nullptr;        // [ldS * ldS]
+
+  // work vectors in device order, row-interleaved [n][nrhs]
+  double* x = nullptr;
+  double* r = nullptr;
+  double* z = nullptr;
+  double* p[2] = {nullptr, nullptr};
+  double* q = nullptr;
+  double* bpart = nullptr;  // [2 NL][nrhs]
+  double* eta = nullptr;    // [ldS][nrhs]
+  PcgScalars* sc = nullptr; // [kMaxNRHS]
+  PcgShared* shared = nullptr;
+  int32_t* h_flags = nullptr;  // pinned host mirror of shared
+  Reduce red;
+
+  // captured PCG chunk
+  hipGraphExec_t graph = nullptr;
+  hipStream_t graph_stream = nullptr;
+  int graph_nrhs = 0;
+  const void* graph_key = nullptr;
+  std::vector<void*> allocs;
+};
+
+// ---- launchers (kernels_local.hip) ----
+hipError_t launch_band_factor(DeviceState& d, hipStream_t s);
+hipError_t launch_mbf(DeviceState& d, hipStream_t s);
+// z = A_i^{-1} r (+ prolongation with eta when eta != nullptr); dots when dot_out
+hipError_t launch_local_sweep(DeviceState& d, const double* r, double* z, const double* eta,
+                              int nrhs, int mode, hipStream_t s);
+hipError_t launch_bpart(DeviceState& d, const double* r, int nrhs, hipStream_t s);
+
+// ---- launchers (kernels_iface.hip) ----
+hipError_t launch_assemble_S(DeviceState& d, hipStream_t s);
+hipError_t dense_cholesky_inverse(DeviceState& d, double* L, double* Linv, hipStream_t s);
+hipError_t launch_iface_gemv(DeviceState& d, int nrhs, hipStream_t s);
+
+// ---- launchers (kernels_pcg.hip) ----
+hipError_t launch_permute_in(const int32_t* dperm, int64_t n, const double* src, int64_t ld,
+                             double* dst, int nrhs, hipStream_t s);
+hipError_t launch_permute_out(const int32_t* dperm, int64_t n, const double* src, double* dst,
+                              int64_t ld, int nrhs, hipStream_t s);
+hipError_t launch_fill(double* p, int64_t count, double v, hipStream_t s);
+hipError_t launch_pcg_init(DeviceState& d, int nrhs, double tol, int maxit, int flexible,
+                           hipStream_t s);
+hipError_t launch_pcg_iteration(DeviceState& d, int nrhs, int parity, hipStream_t s);
+hipError_t launch_pcg_start(DeviceState& d, int nrhs, hipStream_t s);
+hipError_t launch_true_residual(DeviceState& d, const double* bperm, int nrhs, double* out2,
+                                hipStream_t s);
+
+// ---- launchers (kernels_tpfa.hip) ----
+struct TpfaDevice {
+  int device = 0;
+  int64_t n = 0, nnz = 0, nf = 0;
+  std::vector<int64_t> h_rp;
+  std::vector<int32_t> h_ci;
+  int64_t* fk = nullptr;   // [nf]
+  int64_t* fl = nullptr;
+  double* gk = nullptr;
+  double* gl = nullptr;
+  double* pD = nullptr;
+  int64_t* slot_kk = nullptr;  // CSR slots touched by each face
+  int64_t* slot_ll = nullptr;
+  int64_t* slot_kl = nullptr;
+  int64_t* slot_lk = nullptr;
+  int64_t* cf_ptr = nullptr;   // cell -> faces CSR
+  int32_t* cf_face = nullptr;
+  std::vector<void*> allocs;
+};
+hipError_t launch_tpfa_assemble(TpfaDevice& t, const double* logK, double* val, double* f,
+                                hipStream_t s);
+hipError_t launch_face_grad(TpfaDevice& t, const double* logK, const double* p,
+                            const double* lam, double* grad, hipStream_t s);
+
+}  // namespace am

@@ -1,0 +1,69 @@
+// Host-side structure of AlgMortar: validation, partitioners, permutation,
+// interface edge sets and mortar numbering (paper Sec. 3.1-3.2), and the
+// device-oriented layout plan derived from them.  Plain C++17, no HIP.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "algmortar.h"
+
+namespace am {
+
+struct HostCSR {
+  int64_t n = 0, nnz = 0;
+  const int64_t* rp = nullptr;
+  const int32_t* ci = nullptr;
+  const double* v = nullptr;
+};
+
+// Validates pattern (monotone row_ptr, strictly ascending in-range columns),
+// finiteness, bitwise symmetry of values (a missing transpose counts as 0)
+// and the sign of every off-diagonal (< 0 or an explicit zero).
+am_status validate_csr(const HostCSR& A, std::string& err);
+am_status validate_partition(int64_t n, const int32_t* part, int32_t nparts, std::string& err);
+
+struct Structure {
+  int64_t n = 0;
+  int32_t m = 0;
+  std::vector<int32_t> part;      // [n]
+  std::vector<int32_t> perm;      // [n] perm[new] = old (ascending inside a part)
+  std::vector<int64_t> sub_ptr;   // [m+1]
+  std::vector<int32_t> edge_k, edge_l;  // [|E|] original indices, k in the lower part
+  std::vector<double> edge_a;           // [|E|] a_kl
+  std::vector<int64_t> iface_ptr;       // [NL+1]
+  std::vector<int32_t> iface_ij;        // [2 NL]
+  std::vector<int64_t> isub_ptr;        // [m+1]   I_i as CSR
+  std::vector<int32_t> isub_list;       // [2 NL]  ascending basis ids per part
+  int64_t n_iface() const { return (int64_t)iface_ptr.size() - 1; }
+  int64_t n_edges() const { return (int64_t)edge_k.size(); }
+};
+
+am_status build_structure(const HostCSR& A, const int32_t* part, int32_t nparts, int mortar,
+                          Structure& st, std::string& err);
+
+am_status partition_blocks(int32_t nx, int32_t ny, int32_t nz, int32_t bx, int32_t by,
+                           int32_t bz, int32_t* part, int32_t* nparts, std::string& err);
+am_status partition_bisect(const HostCSR& A, int32_t lo, int32_t hi, uint64_t seed,
+                           int32_t* part, int32_t* nparts, std::string& err);
+
+uint64_t splitmix64(uint64_t x);
+
+// Band layout of the local factors.  Inside every subdomain the device uses
+// an ordering (identity or reverse Cuthill-McKee, whichever has the smaller
+// bandwidth) and a window width Wp = 64 * ceil(bandwidth / 64).
+struct LocalPlan {
+  std::vector<int32_t> dperm;      // [n] device order: dperm[new] = old
+  std::vector<int32_t> dpos;       // [n] inverse: dpos[old] = new
+  std::vector<int32_t> wp;         // [m] window width per subdomain
+  std::vector<int64_t> roff;       // [m+1] padded row offsets (rows padded to a multiple of 64)
+  std::vector<int64_t> fac_off;    // [m+1] offsets (elements) of Lc / Lr blocks = roff * wp
+  int32_t max_wp = 64;
+  int32_t max_ni = 0;              // max |I_i|
+  int32_t max_sub = 0;             // max subdomain size
+};
+
+am_status plan_local(const HostCSR& A, const Structure& st, LocalPlan& lp, std::string& err);
+
+}  // namespace am

@@ -1,0 +1,367 @@
+// Interface kernels for gfx950: assembly of the interface matrix
+//   S[n, m] = -delta_nm sum_{e in E_n} a_e + sum_{e in E_n} a_e (phat^(m)_k + phat^(m)_l)/2
+// (eq. interface-problem-alg with the sign of Corollary eq. k-schur), its
+// symmetrisation, an FP64 tiled Cholesky S = L L^T followed by the explicit
+// inverse S^{-1} = L^{-T} L^{-1}, and the per-apply interface solve
+// eta = S^{-1} b as a dense GEMV/GEMM (Algorithm 2).
+//
+// Dense tiles are 64 x 64, row-major with leading dimension ldS (a multiple
+// of 64); rows/columns beyond N_Lambda hold the identity.
+#include "am_common.h"
+
+namespace am {
+
+// ---------------------------------------------------------------------------
+// One wave per interface row n.  Every write to row n comes from lane 0 of
+// that wave, in a fixed order.
+__global__ __launch_bounds__(256) void k_assemble_S(
+    int NL, int ldS, const int64_t* __restrict__ iface_ptr, const int32_t* __restrict__ iface_ij,
+    const int32_t* __restrict__ e_kloc, const int32_t* __restrict__ e_lloc,
+    const double* __restrict__ e_a, const int64_t* __restrict__ sub_ptr,
+    const int64_t* __restrict__ isub_ptr, const int32_t* __restrict__ isub_list,
+    const int64_t* __restrict__ mbf_off, const double* __restrict__ mbf, double* S) {
+  const int lane = threadIdx.x & 63;
+  const int n = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (n >= NL) return;
+  const int i = iface_ij[2 * n], j = iface_ij[2 * n + 1];
+  const int64_t e0 = iface_ptr[n], e1 = iface_ptr[n + 1];
+  double sa = 0.0;
+  for (int64_t e = e0 + lane; e < e1; e += 64) sa += e_a[e];
+  sa = wave_sum(sa);
+  double* Srow = S + (size_t)n * ldS;
+  for (int side = 0; side < 2; ++side) {
+    const int sd = side == 0 ? i : j;
+    const int Ns = (int)(sub_ptr[sd + 1] - sub_ptr[sd]);
+    const double* P = mbf + mbf_off[sd];
+    const int32_t* loc = side == 0 ? e_kloc : e_lloc;
+    const int64_t q0 = isub_ptr[sd];
+    const int nq = (int)(isub_ptr[sd + 1] - q0);
+    for (int q = 0; q < nq; ++q) {
+      const int m = isub_list[q0 + q];
+      double v = 0.0;
+      for (int64_t e = e0 + lane; e < e1; e += 64) v = fma(e_a[e], P[(size_t)q * Ns + loc[e]], v);
+      v = wave_sum(v);
+      if (lane == 0) Srow[m] += 0.5 * v;
+    }
+  }
+  if (lane == 0) Srow[n] -= sa;
+}
+
+// (S + S^T)/2 on the N_Lambda block; identity on the padding.
+__global__ __launch_bounds__(256) void k_symmetrize(int NL, int ldS, double* S) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tot = (int64_t)ldS * ldS;
+  if (t >= tot) return;
+  const int r = (int)(t / ldS), c = (int)(t % ldS);
+  if (r >= NL || c >= NL) {
+    if (r == c) S[t] = 1.0;
+    return;
+  }
+  if (r <= c) return;
+  const double v = 0.5 * (S[(size_t)r * ldS + c] + S[(size_t)c * ldS + r]);
+  S[(size_t)r * ldS + c] = v;
+  S[(size_t)c * ldS + r] = v;
+}
+
+// ---------------------------------------------------------------------------
+// dense tile helpers (64 x 64, 256 threads, 4 x 4 outputs per thread)
+typedef double Tile[64][65];
+
+__device__ __forceinline__ void load_tile(Tile& T, const double* p, int ld, bool trans) {
+  for (int t = threadIdx.x; t < 4096; t += blockDim.x) {
+    const int r = t >> 6, c = t & 63;
+    if (trans)
+      T[c][r] = p[(size_t)r * ld + c];
+    else
+      T[r][c] = p[(size_t)r * ld + c];
+  }
+}
+
+// acc += A * B for the thread's 4 x 4 block (rows 4*ty.., cols 4*tx..)
+__device__ __forceinline__ void tile_mac(double (&acc)[4][4], const Tile& A, const Tile& B) {
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+#pragma unroll 4
+  for (int k = 0; k < 64; ++k) {
+    double a[4], b[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = A[4 * ty + i][k];
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) b[jj] = B[k][4 * tx + jj];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) acc[i][jj] = fma(a[i], b[jj], acc[i][jj]);
+  }
+}
+
+__device__ __forceinline__ void zero_acc(double (&acc)[4][4]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) acc[i][jj] = 0.0;
+}
+
+// Cholesky of the diagonal tile (b, b), in place (lower; upper zeroed).
+__global__ __launch_bounds__(256) void k_potrf_diag(double* A, int ld, int b, int32_t* fail) {
+  __shared__ Tile T;
+  double* p = A + (size_t)b * 64 * ld + (size_t)b * 64;
+  load_tile(T, p, ld, false);
+  __syncthreads();
+  const int tid = threadIdx.x;
+  for (int k = 0; k < 64; ++k) {
+    const double d = T[k][k];
+    const bool bad = !(d > 0.0);
+    const double ljj = bad ? 1.0 : sqrt(d);
+    __syncthreads();
+    if (tid == 0) {
+      T[k][k] = ljj;
+      if (bad && atomicCAS(fail, -1, b * 64 + k) == -1) fail[1] = b * 64 + k;
+    }
+    if (tid > k && tid < 64) T[tid][k] /= ljj;
+    __syncthreads();
+    for (int t = tid; t < 4096; t += blockDim.x) {
+      const int i = t >> 6, jj = t & 63;
+      if (jj > k && jj <= i) T[i][jj] -= T[i][k] * T[jj][k];
+    }
+    __syncthreads();
+  }
+  for (int t = tid; t < 4096; t += blockDim.x) {
+    const int r = t >> 6, c = t & 63;
+    p[(size_t)r * ld + c] = c <= r ? T[r][c] : 0.0;
+  }
+}
+
+// Panel: A_ib <- A_ib L_bb^{-T} for i = b+1.. (one tile per block, one row per thread).
+__global__ __launch_bounds__(64) void k_trsm_panel(double* A, int ld, int b) {
+  __shared__ Tile L;
+  __shared__ Tile X;
+  const int i = b + 1 + blockIdx.x;
+  const double* pl = A + (size_t)b * 64 * ld + (size_t)b * 64;
+  double* pa = A + (size_t)i * 64 * ld + (size_t)b * 64;
+  load_tile(L, pl, ld, false);
+  load_tile(X, pa, ld, false);
+  __syncthreads();
+  const int r = threadIdx.x;
+  for (int c = 0; c < 64; ++c) {
+    double v = X[r][c];
+    for (int k = 0; k < c; ++k) v -= X[r][k] * L[c][k];
+    X[r][c] = v / L[c][c];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < 4096; t += blockDim.x) {
+    const int rr = t >> 6, c = t & 63;
+    pa[(size_t)rr * ld + c] = X[rr][c];
+  }
+}
+
+// Trailing update A_ij -= A_ib A_jb^T for b < j <= i.
+__global__ __launch_bounds__(256) void k_syrk_update(double* A, int ld, int b) {
+  const int j = b + 1 + blockIdx.x, i = b + 1 + blockIdx.y;
+  if (j > i) return;
+  __shared__ Tile Ai;
+  __shared__ Tile Bj;
+  load_tile(Ai, A + (size_t)i * 64 * ld + (size_t)b * 64, ld, false);
+  load_tile(Bj, A + (size_t)j * 64 * ld + (size_t)b * 64, ld, true);
+  __syncthreads();
+  double acc[4][4];
+  zero_acc(acc);
+  tile_mac(acc, Ai, Bj);
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double* pc = A + (size_t)i * 64 * ld + (size_t)j * 64;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) pc[(size_t)(4 * ty + r) * ld + 4 * tx + c] -= acc[r][c];
+}
+
+// Inverse of each diagonal tile of L (lower), one column per thread.
+__global__ __launch_bounds__(64) void k_trtri_diag(const double* L, double* Li, int ld) {
+  __shared__ Tile T;
+  __shared__ Tile X;
+  const int b = blockIdx.x;
+  load_tile(T, L + (size_t)b * 64 * ld + (size_t)b * 64, ld, false);
+  __syncthreads();
+  const int c = threadIdx.x;
+  for (int r = 0; r < 64; ++r) {
+    double v = (r == c) ? 1.0 : 0.0;
+    if (r < c) {
+      X[r][c] = 0.0;
+      continue;
+    }
+    for (int k = c; k < r; ++k) v -= T[r][k] * X[k][c];
+    X[r][c] = v / T[r][r];
+  }
+  __syncthreads();
+  double* p = Li + (size_t)b * 64 * ld + (size_t)b * 64;
+  for (int t = threadIdx.x; t < 4096; t += blockDim.x) {
+    const int r = t >> 6, cc = t & 63;
+    p[(size_t)r * ld + cc] = X[r][cc];
+  }
+}
+
+// Off-diagonal tiles of L^{-1} at distance d: Li_ij = -Li_ii sum_{k=j}^{i-1} L_ik Li_kj.
+__global__ __launch_bounds__(256) void k_trtri_off(const double* L, double* Li, int ld, int d) {
+  const int i = d + blockIdx.x, j = blockIdx.x;
+  __shared__ Tile As;
+  __shared__ Tile Bs;
+  double acc[4][4];
+  zero_acc(acc);
+  for (int k = j; k < i; ++k) {
+    load_tile(As, L + (size_t)i * 64 * ld + (size_t)k * 64, ld, false);
+    load_tile(Bs, Li + (size_t)k * 64 * ld + (size_t)j * 64, ld, false);
+    __syncthreads();
+    tile_mac(acc, As, Bs);
+    __syncthreads();
+  }
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) Bs[4 * ty + r][4 * tx + c] = acc[r][c];
+  load_tile(As, Li + (size_t)i * 64 * ld + (size_t)i * 64, ld, false);
+  __syncthreads();
+  zero_acc(acc);
+  tile_mac(acc, As, Bs);
+  double* p = Li + (size_t)i * 64 * ld + (size_t)j * 64;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) p[(size_t)(4 * ty + r) * ld + 4 * tx + c] = -acc[r][c];
+}
+
+// S^{-1}_ij = sum_{k >= max(i,j)} Li_ki^T Li_kj for i >= j, mirrored.
+__global__ __launch_bounds__(256) void k_lauum(const double* Li, double* Sinv, int ld, int T) {
+  const int j = blockIdx.x, i = blockIdx.y;
+  if (j > i) return;
+  __shared__ Tile As;
+  __shared__ Tile Bs;
+  double acc[4][4];
+  zero_acc(acc);
+  for (int k = i; k < T; ++k) {
+    load_tile(As, Li + (size_t)k * 64 * ld + (size_t)i * 64, ld, true);
+    load_tile(Bs, Li + (size_t)k * 64 * ld + (size_t)j * 64, ld, false);
+    __syncthreads();
+    tile_mac(acc, As, Bs);
+    __syncthreads();
+  }
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const size_t gr = (size_t)i * 64 + 4 * ty + r, gc = (size_t)j * 64 + 4 * tx + c;
+      if (gr < gc) continue;  // diagonal tile: the lower half defines both halves
+      Sinv[gr * ld + gc] = acc[r][c];
+      Sinv[gc * ld + gr] = acc[r][c];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// eta = S^{-1} b, b_m = bpart[bidx[2m]] + bpart[bidx[2m+1]].  Each wave owns
+// ROWS rows of S^{-1}; b is staged through LDS in chunks.
+template <int NR, int ROWS>
+__global__ __launch_bounds__(256) void k_iface_gemv(int NL, int ldS, const double* __restrict__ Sinv,
+                                                    const double* __restrict__ bpart,
+                                                    const int64_t* __restrict__ bidx, double* eta,
+                                                    const PcgShared* sh, int check_done) {
+  if (check_done && all_done(sh)) return;
+  constexpr int CH = NR <= 2 ? 1024 : (NR <= 4 ? 512 : 256);
+  __shared__ double bs[CH * NR];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int n0 = (blockIdx.x * 4 + w) * ROWS;
+  double acc[ROWS][NR];
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+    for (int k = 0; k < NR; ++k) acc[r][k] = 0.0;
+  for (int m0 = 0; m0 < NL; m0 += CH) {
+    const int cnt = min(CH, NL - m0);
+    for (int t = threadIdx.x; t < cnt * NR; t += blockDim.x) {
+      const int m = m0 + t / NR, k = t % NR;
+      bs[t] = bpart[(size_t)bidx[2 * m] * NR + k] + bpart[(size_t)bidx[2 * m + 1] * NR + k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+      const int n = n0 + r;
+      if (n < NL) {
+        const double* row = Sinv + (size_t)n * ldS + m0;
+        for (int mm = lane; mm < cnt; mm += 64) {
+          const double sv = row[mm];
+#pragma unroll
+          for (int k = 0; k < NR; ++k) acc[r][k] = fma(sv, bs[mm * NR + k], acc[r][k]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r) {
+    const int n = n0 + r;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      const double v = wave_sum(acc[r][k]);
+      if (lane == 0 && n < NL) eta[(size_t)n * NR + k] = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+hipError_t launch_assemble_S(DeviceState& d, hipStream_t st) {
+  if (d.NL == 0) return hipSuccess;
+  hipError_t e = hipMemsetAsync(d.S, 0, sizeof(double) * (size_t)d.ldS * d.ldS, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_assemble_S, dim3((unsigned)((d.NL + 3) / 4)), dim3(256), 0, st, (int)d.NL,
+                     d.ldS, d.iface_ptr, d.iface_ij, d.e_kloc, d.e_lloc, d.e_a, d.sub_ptr,
+                     d.isub_ptr, d.isub_list, d.mbf_off, d.mbf, d.S);
+  const int64_t tot = (int64_t)d.ldS * d.ldS;
+  hipLaunchKernelGGL(k_symmetrize, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
+                     (int)d.NL, d.ldS, d.S);
+  return hipGetLastError();
+}
+
+hipError_t dense_cholesky_inverse(DeviceState& d, double* L, double* Li, hipStream_t st) {
+  const int ld = d.ldS, T = ld / 64;
+  if (T == 0) return hipSuccess;
+  hipError_t e = hipMemcpyAsync(L, d.S, sizeof(double) * (size_t)ld * ld, hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return e;
+  e = hipMemsetAsync(Li, 0, sizeof(double) * (size_t)ld * ld, st);
+  if (e != hipSuccess) return e;
+  for (int b = 0; b < T; ++b) {
+    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, st, L, ld, b, d.fail + 2);
+    if (b + 1 < T) {
+      hipLaunchKernelGGL(k_trsm_panel, dim3(T - b - 1), dim3(64), 0, st, L, ld, b);
+      hipLaunchKernelGGL(k_syrk_update, dim3(T - b - 1, T - b - 1), dim3(256), 0, st, L, ld, b);
+    }
+  }
+  hipLaunchKernelGGL(k_trtri_diag, dim3(T), dim3(64), 0, st, L, Li, ld);
+  for (int dd = 1; dd < T; ++dd)
+    hipLaunchKernelGGL(k_trtri_off, dim3(T - dd), dim3(256), 0, st, L, Li, ld, dd);
+  hipLaunchKernelGGL(k_lauum, dim3(T, T), dim3(256), 0, st, Li, d.Sinv, ld, T);
+  return hipGetLastError();
+}
+
+template <int NR>
+static void gemv_t(DeviceState& d, hipStream_t st, int check) {
+  constexpr int ROWS = 1;
+  const unsigned nb = (unsigned)((d.NL + 4 * ROWS - 1) / (4 * ROWS));
+  hipLaunchKernelGGL((k_iface_gemv<NR, ROWS>), dim3(nb), dim3(256), 0, st, (int)d.NL, d.ldS,
+                     d.Sinv, d.bpart, d.bidx, d.eta, d.shared, check);
+}
+
+hipError_t launch_iface_gemv(DeviceState& d, int nrhs, hipStream_t st) {
+  if (d.NL == 0) return hipSuccess;
+  const int check = nrhs < 0 ? 1 : 0;
+  const int nr = nrhs < 0 ? -nrhs : nrhs;
+  switch (nr) {
+    case 1: gemv_t<1>(d, st, check); break;
+    case 2: gemv_t<2>(d, st, check); break;
+    case 4: gemv_t<4>(d, st, check); break;
+    case 8: gemv_t<8>(d, st, check); break;
+    case 16: gemv_t<16>(d, st, check); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace am

@@ -9,6 +9,9 @@ the shared input generators).
   bit), plus their sizes.
 * ``c1_pcg.json``: iteration count and solution norms of the oracle's
   AlgMortar-PCG on the 2-D workload (tol 1e-10).
+* ``c2_pcg.json``: the 64^3 layered workload (the benchmark's): the oracle's
+  apply of a seeded N(0,1) vector and its PCG solution at the workload's
+  tolerance (1e-8), as norms plus values at 256 seeded cells.
 """
 import hashlib
 import json
@@ -63,5 +66,24 @@ def main():
     print(rec)
 
 
+def c2_record():
+    P = make_config("c2")
+    part, _ = partition_blocks(P.dims, P.partition[1])
+    pre = AlgMortarCPU(P.A, part)
+    idx = np.sort(np.random.default_rng(7).choice(P.n, size=256, replace=False))
+    r = np.random.default_rng(11).standard_normal(P.n)
+    z = pre.apply(r)
+    As = P.A.to_scipy()
+    res = pcg(lambda v: As @ v, P.b, pre.apply, P.tol)
+    rec = dict(apply_seed=11, sample_idx=idx.tolist(), apply_sample=z[idx].tolist(),
+               apply_norm=float(np.linalg.norm(z)), iterations=res.iterations,
+               x_sample=res.x[idx].tolist(), x_norm2=float(np.linalg.norm(res.x)),
+               true_rel_res=res.true_rel_res, tol=P.tol)
+    with open(os.path.join(HERE, "c2_pcg.json"), "w") as f:
+        json.dump(rec, f, indent=1, sort_keys=True)
+    print("c2", res.iterations, res.true_rel_res)
+
+
 if __name__ == "__main__":
     main()
+    c2_record()

@@ -1,0 +1,232 @@
+"""GPU parity of the HIP path against the FP64 oracle (all calls go through
+the C-ABI).  Tolerances: bit-exact for index structure; 1e-12 relative L2 for
+local solves and preconditioner applies; PCG solutions within 1e-8 relative
+L2 at tolerance 1e-10 (the method's stated parity bars)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+import paper_2607_22905_amd as am  # noqa: E402
+from paper_2607_22905_amd import AlgMortarError  # noqa: E402
+from oracle import AlgMortarCPU, partition_blocks, partition_bisect, pcg  # noqa: E402
+from workloads import make_config  # noqa: E402
+from workloads.grids import cartesian_faces, distorted_hex_faces  # noqa: E402
+from workloads.tpfa import Faces, assemble, CSR  # noqa: E402
+from tests._problems import random_3d, random_2d, dense_csr  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def gpu(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=DEV)
+
+
+def cpu(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _case(name):
+    """(A, part, nparts, label) for the parity cases: several tiles and
+    ragged subdomain sizes (not multiples of 64) and a bisection partition
+    with reverse Cuthill-McKee local orderings."""
+    if name == "c1":
+        P = make_config("c1")
+        part, m = partition_blocks(P.dims, P.partition[1])
+        return P.A, part, m, P.b
+    if name == "ragged3d":
+        P = random_3d(18, 15, 8, 1.5, 11, block=(6, 5, 4))  # 120-cell blocks
+        part, m = partition_blocks(P.dims, P.partition[1])
+        return P.A, part, m, P.b
+    if name == "layered":
+        P = make_config("c2", nx=32, ny=32, nz=32)
+        part, m = partition_blocks(P.dims, P.partition[1])
+        return P.A, part, m, P.b
+    if name == "bisect":
+        nx, ny, nz = 40, 30, 12
+        n = nx * ny * nz
+        f = Faces.from_dict(distorted_hex_faces(nx, ny, nz, 0.3, 4, [(0, 0, 0.0)]))
+        g = np.random.default_rng(4).normal(size=n) * 1.5
+        src = np.zeros(n)
+        src[[5, n - 7]] = [1.0, -1.0]
+        A, b = assemble(f, np.exp(g), n, src)
+        part, m = partition_bisect(A.row_ptr, A.col, A.val, n, 200, 800, 4)
+        return A, part, m, b
+    raise KeyError(name)
+
+
+CASES = ["c1", "ragged3d", "layered", "bisect"]
+_cache = {}
+
+
+def setup_case(name):
+    if name not in _cache:
+        A, part, m, b = _case(name)
+        _cache[name] = (A, part, m, b, AlgMortarCPU(A, part))
+    return _cache[name]
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_interfaces_bit_exact(name):
+    A, part, m, b, ora = setup_case(name)
+    h = am.AlgMortar(A, part, m)
+    s = h.interfaces()
+    st = ora.st
+    for k in ("perm", "sub_ptr", "iface_ptr", "edge_k", "edge_l"):
+        assert np.array_equal(s[k], getattr(st, k)), k
+    assert np.array_equal(s["iface_ij"], st.iface_ij)
+    h.close()
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_local_solve_parity(name):
+    A, part, m, b, ora = setup_case(name)
+    h = am.AlgMortar(A, part, m)
+    r = np.random.default_rng(1).standard_normal(A.n)
+    pb = cpu(h.local_solve(gpu(r)))
+    assert rel(pb, ora.local_solves(r)) <= 1e-12
+    h.close()
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_mbf_and_interface_matrix_parity(name):
+    A, part, m, b, ora = setup_case(name)
+    h = am.AlgMortar(A, part, m)
+    st = ora.st
+    for nidx in range(0, st.n_iface, max(1, st.n_iface // 7)):
+        i, j = st.iface_ij[nidx]
+        for s in (int(i), int(j)):
+            N = int(st.sub_ptr[s + 1] - st.sub_ptr[s])
+            v = h.export_mbf(nidx, s, N)
+            assert rel(v, ora.phat[nidx][s]) <= 1e-12
+    S = h.export_interface("S")
+    Sd = ora.S.toarray()
+    assert np.abs(S - Sd).max() <= 1e-12 * np.abs(Sd).max()
+    Si = h.export_interface("Sinv")
+    assert np.abs(Si @ Sd - np.eye(Sd.shape[0])).max() <= 1e-9
+    h.close()
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_apply_parity(name):
+    A, part, m, b, ora = setup_case(name)
+    h = am.AlgMortar(A, part, m, max_nrhs=4)
+    rng = np.random.default_rng(2)
+    for r in [b, rng.standard_normal(A.n), rng.standard_normal(A.n)]:
+        z = cpu(h.apply(gpu(r)))
+        assert rel(z, ora.apply(r)) <= 1e-12
+    R = rng.standard_normal((3, A.n))
+    Z = cpu(h.apply(gpu(R)))
+    for c in range(3):
+        assert rel(Z[c], ora.apply(R[c])) <= 1e-12
+    h.close()
+
+
+def test_apply_per_edge_mortar_is_direct_solve():
+    P = random_3d(8, 6, 4, 1.0, 3, block=(4, 3, 2))
+    part, m = partition_blocks(P.dims, P.partition[1])
+    h = am.AlgMortar(P.A, part, m, mortar="edge")
+    r = np.random.default_rng(3).standard_normal(P.n)
+    z = cpu(h.apply(gpu(r)))
+    zd = np.linalg.solve(P.A.to_scipy().toarray(), r)
+    assert rel(z, zd) <= 1e-11
+    h.close()
+
+
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("graph", [True, False])
+def test_pcg_parity(name, graph):
+    A, part, m, b, ora = setup_case(name)
+    h = am.AlgMortar(A, part, m, graph=graph)
+    As = A.to_scipy()
+    ref = pcg(lambda v: As @ v, b, ora.apply, 1e-10)
+    x, info, st = h.pcg(gpu(b), 1e-10)
+    x = cpu(x)
+    assert info[0]["converged"] == 1
+    assert abs(info[0]["iterations"] - ref.iterations) <= 1
+    assert rel(x, ref.x) <= 1e-8
+    assert info[0]["true_rel_res"] <= 1e-9
+    h.close()
+
+
+def test_pcg_deterministic_and_multi_rhs():
+    A, part, m, b, ora = setup_case("ragged3d")
+    h = am.AlgMortar(A, part, m, max_nrhs=4)
+    x1 = cpu(h.pcg(gpu(b), 1e-10)[0])
+    x2 = cpu(h.pcg(gpu(b), 1e-10)[0])
+    assert np.array_equal(x1, x2)
+    rng = np.random.default_rng(5)
+    B = np.stack([b, rng.standard_normal(A.n), rng.standard_normal(A.n)])
+    X, infos, _ = h.pcg(gpu(B), 1e-10)
+    X = cpu(X)
+    As = A.to_scipy()
+    for c in range(3):
+        ref = pcg(lambda v: As @ v, B[c], ora.apply, 1e-10)
+        assert rel(X[c], ref.x) <= 1e-8
+        assert abs(infos[c]["iterations"] - ref.iterations) <= 1
+    h.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_reduced_precision_forms_converge(prec):
+    A, part, m, b, ora = setup_case("layered")
+    As = A.to_scipy()
+    ref = pcg(lambda v: As @ v, b, ora.apply, 1e-10)
+    h = am.AlgMortar(A, part, m, prec=prec)
+    x, info, _ = h.pcg(gpu(b), 1e-10)
+    x = cpu(x)
+    assert info[0]["converged"] == 1 and info[0]["true_rel_res"] <= 1e-9
+    assert rel(x, ref.x) <= 1e-8
+    # the preconditioner is a perturbed AlgMortar: iteration count stays close
+    assert info[0]["iterations"] <= ref.iterations * 1.5 + 5
+    h.close()
+
+
+def test_not_spd_reported():
+    Ad = np.array([[1.0, -2.0, 0.0], [-2.0, 1.0, -0.5], [0.0, -0.5, 2.0]])
+    A = dense_csr(Ad)
+    with pytest.raises(AlgMortarError) as ei:
+        am.AlgMortar(A, np.zeros(3, np.int32), 1)
+    assert ei.value.status_name == "AM_ERR_NOT_SPD"
+
+
+def test_no_convergence_reported():
+    A, part, m, b, ora = setup_case("c1")
+    h = am.AlgMortar(A, part, m)
+    x, info, st = h.pcg(gpu(b), 1e-10, maxit=3, raise_on_error=False)
+    assert st == -5 and info[0]["iterations"] == 3 and info[0]["converged"] == 0
+    h.close()
+
+
+def test_c2_full_size_apply_and_pcg():
+    """The benchmark workload (64^3 layered, 512 subdomains) at full size:
+    apply parity with the oracle on a seeded vector; PCG true residual and
+    iteration count against the oracle's stored record."""
+    import json
+    import os
+    P = make_config("c2")
+    part, m = partition_blocks(P.dims, P.partition[1])
+    h = am.AlgMortar(P.A, part, m)
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c2_pcg.json")))
+    r = np.random.default_rng(gold["apply_seed"]).standard_normal(P.n)
+    z = cpu(h.apply(gpu(r)))
+    idx = np.array(gold["sample_idx"])
+    zs = np.array(gold["apply_sample"])
+    assert np.abs(z[idx] - zs).max() <= 1e-12 * np.abs(zs).max()
+    assert abs(np.linalg.norm(z) - gold["apply_norm"]) <= 1e-12 * gold["apply_norm"]
+    x, info, _ = h.pcg(gpu(P.b), P.tol)
+    x = cpu(x)
+    assert info[0]["converged"] == 1
+    assert abs(info[0]["iterations"] - gold["iterations"]) <= 1
+    tr = np.linalg.norm(P.b - P.A.to_scipy() @ x) / np.linalg.norm(P.b)
+    assert tr <= 2 * P.tol
+    xs = np.array(gold["x_sample"])
+    assert np.abs(x[idx] - xs).max() <= 1e-6 * np.abs(xs).max()
+    h.close()
