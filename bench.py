@@ -87,6 +87,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=12)
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -99,6 +101,13 @@ def main():
     import paper_2607_22905_amd as am
     from workloads import make_config
 
+    if args.calibrate_copy:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     log(f"bench: building workload {args.config}")
     P = make_config(args.config)
     if P.partition[0] == "blocks":
@@ -131,7 +140,13 @@ def main():
     k_ms, k_bytes = h.time_kernel("local", reps=50)
     achieved = k_bytes / (k_ms * 1e-3) / 1e9
     g_ms, g_bytes = h.time_kernel("gemv", reps=50)
-    log(f"bench: local kernel {k_ms * 1e3:.1f} us, gemv {g_ms * 1e3:.1f} us")
+    others = {}
+    for name in ("spmv", "update", "bpart"):
+        ms_, by_ = h.time_kernel(name, reps=50)
+        others[name] = {"avg_launch_us": ms_ * 1e3, "bytes_per_launch": by_,
+                        "achieved_GBs": by_ / (ms_ * 1e-3) / 1e9}
+    log(f"bench: local kernel {k_ms * 1e3:.1f} us, gemv {g_ms * 1e3:.1f} us, "
+        + ", ".join(f"{k} {v['avg_launch_us']:.1f} us" for k, v in others.items()))
     traffic = traffic_record(args.prec, args.config)
     out = {
         "metric": "PCG solves/s to 1e-8 rel. residual; precond-apply HBM GB/s vs peak",
@@ -160,6 +175,7 @@ def main():
                      "avg_launch_us": k_ms * 1e3, "bytes_per_launch": k_bytes},
         "iface_gemv": {"avg_launch_us": g_ms * 1e3, "bytes_per_launch": g_bytes,
                        "achieved_GBs": g_bytes / (g_ms * 1e-3) / 1e9},
+        "other_kernels": others,
     }
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")

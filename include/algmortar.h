@@ -200,7 +200,10 @@ am_status algmortar_export_mbf(am_handle h, int64_t iface, int32_t sub, double* 
  * handle's internal stream, bracketed by HIP events (the buffers hold the
  * last call's data).  kernel: 0 = local solves + reconstruction (the band
  * sweeps of Algorithm 2), 1 = interface solve eta = S^{-1} b (GEMV),
- * 2 = interface partial right-hand sides.  avg_ms: host (out), average launch
+ * 2 = interface partial right-hand sides, 3 = the PCG SpMV (p update, A p,
+ * (p, Ap)), 4 = the PCG x/r update with the interface partials.  Timing 3
+ * or 4 leaves the handle's PCG scalars in an unspecified state (the next
+ * algmortar_pcg call re-initialises them).  avg_ms: host (out), average launch
  * duration; bytes: host (out), the kernel's algorithmic HBM bytes per launch
  * (factor, vectors and operators it must read or write once). */
 am_status algmortar_time_kernel(am_handle h, int32_t kernel, int32_t nrhs, int32_t reps,

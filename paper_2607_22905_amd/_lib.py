@@ -4,7 +4,7 @@ import os
 from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_uint32, c_uint64, c_void_p
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libalgmortar.so")
+LIB_PATH = os.environ.get("ALGMORTAR_LIB", os.path.join(HERE, "libalgmortar.so"))
 
 AM_OK = 0
 STATUS_NAMES = {

@@ -14,8 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
-BUILD = os.path.join(HERE, "_build")
-LIB = os.path.join(HERE, "libalgmortar.so")
+BUILD = os.environ.get("ALGMORTAR_BUILD_DIR", os.path.join(HERE, "_build"))
+LIB = os.environ.get("ALGMORTAR_LIB", os.path.join(HERE, "libalgmortar.so"))
 
 SOURCES = [
     "host_structure.cpp",
@@ -34,10 +34,13 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE,
           "-Wno-unused-command-line-argument"]
 
 
+EXTRA = os.environ.get("ALGMORTAR_CFLAGS", "").split()
+
+
 def _compile(src):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     lang = ["-x", "hip"] if src.endswith(".hip") else []
-    cmd = [HIPCC] + COMMON + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC] + COMMON + EXTRA + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile of {src} failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

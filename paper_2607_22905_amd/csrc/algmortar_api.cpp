@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -25,6 +26,7 @@ struct am_handle_s {
   DeviceState d;
   hipStream_t own = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t evf[2] = {nullptr, nullptr};  // stop-flag copies of consecutive chunks
   double* tres = nullptr;  // [kMaxNRHS] ||b - Ax||^2
   double* bp = nullptr;    // permuted right-hand side
 };
@@ -188,6 +190,8 @@ am_status algmortar_destroy(am_handle h) {
   if (h->d.h_flags) hipHostFree(h->d.h_flags);
   if (h->ev0) hipEventDestroy(h->ev0);
   if (h->ev1) hipEventDestroy(h->ev1);
+  for (hipEvent_t e : h->evf)
+    if (e) hipEventDestroy(e);
   if (h->own) hipStreamDestroy(h->own);
   delete h;
   return AM_OK;
@@ -241,6 +245,10 @@ am_status algmortar_setup(const am_csr* A, const int32_t* part, int32_t nparts,
   d.NE = st.n_edges();
   d.ldS = (int32_t)((d.NL + kTile - 1) / kTile * kTile);
   d.max_nrhs = pow2_at_least(opt.max_nrhs);
+  // small interface inverses are applied inside the local kernel (each
+  // subdomain multiplies its own rows; every row is read twice)
+  d.fuse_eta = (d.NL > 0 && (double)d.NL * d.NL * 8.0 <= 64.0 * 1024 * 1024) ? 1 : 0;
+  if (const char* env = getenv("ALGMORTAR_FUSE_ETA")) d.fuse_eta = atoi(env) && d.NL > 0;
 
   auto hipfail = [&](hipError_t he, const char* what) {
     fail(h, he == hipErrorOutOfMemory ? AM_ERR_OOM : AM_ERR_HIP,
@@ -257,6 +265,8 @@ am_status algmortar_setup(const am_csr* A, const int32_t* part, int32_t nparts,
   SCHK(hipStreamCreateWithFlags(&h->own, hipStreamNonBlocking));
   SCHK(hipEventCreate(&h->ev0));
   SCHK(hipEventCreate(&h->ev1));
+  SCHK(hipEventCreateWithFlags(&h->evf[0], hipEventDisableTiming));
+  SCHK(hipEventCreateWithFlags(&h->evf[1], hipEventDisableTiming));
   hipStream_t sm = h->own;
   if (stream) SCHK(hipStreamSynchronize((hipStream_t)stream));
 
@@ -305,16 +315,16 @@ am_status algmortar_setup(const am_csr* A, const int32_t* part, int32_t nparts,
   const int64_t NL = d.NL;
   const int64_t npair = 2 * NL;
   std::vector<int32_t> pair_sub(npair), pair_q(npair);
-  std::vector<int64_t> bidx(npair);
+  std::vector<int64_t> bidx(npair);  // (interface, side) -> pair
+  std::vector<int64_t> bdst(npair);  // pair -> (interface, side) slot 2n + side
   for (int32_t s2 = 0; s2 < st.m; ++s2)
     for (int64_t pi = st.isub_ptr[s2]; pi < st.isub_ptr[s2 + 1]; ++pi) {
       pair_sub[pi] = s2;
       pair_q[pi] = (int32_t)(pi - st.isub_ptr[s2]);
       const int32_t nidx = st.isub_list[pi];
-      if (st.iface_ij[2 * nidx] == s2)
-        bidx[2 * nidx] = pi;
-      else
-        bidx[2 * nidx + 1] = pi;
+      const int side = st.iface_ij[2 * nidx] == s2 ? 0 : 1;
+      bidx[2 * nidx + side] = pi;
+      bdst[pi] = 2 * (int64_t)nidx + side;
     }
   for (int bk = 0; bk < 2; ++bk) d.bucket_pair[bk].clear();
   for (int64_t pi = 0; pi < npair; ++pi)
@@ -387,7 +397,7 @@ am_status algmortar_setup(const am_csr* A, const int32_t* part, int32_t nparts,
   SCHK(upload(al, &d.e_kloc, e_kloc, sm));
   SCHK(upload(al, &d.e_lloc, e_lloc, sm));
   SCHK(upload(al, &d.e_a, st.edge_a, sm));
-  SCHK(upload(al, &d.bidx, bidx, sm));
+  SCHK(upload(al, &d.bdst, bdst, sm));
   std::vector<double>().swap(ell_val);
   std::vector<int32_t>().swap(ell_col);
 
@@ -425,7 +435,11 @@ am_status algmortar_setup(const am_csr* A, const int32_t* part, int32_t nparts,
   SCHK(dalloc(al, &d.shared, 1));
   SCHK(dalloc(al, &h->tres, kMaxNRHS));
   d.red.max_blocks = (int)std::max<int64_t>((n + 255) / 256, st.m) + 1;
+  d.red.spmv_blocks = (int)std::min<int64_t>((n + 255) / 256, 1024);
   SCHK(dalloc(al, &d.red.partial, (size_t)d.red.max_blocks * 2 * kMaxNRHS));
+  SCHK(dalloc(al, &d.red.pa, (size_t)d.red.spmv_blocks * kMaxNRHS));
+  SCHK(dalloc(al, &d.red.pb, (size_t)st.m * kMaxNRHS));
+  SCHK(dalloc(al, &d.red.pd, (size_t)st.m * 2 * kMaxNRHS));
   SCHK(dalloc(al, &d.red.counter, 8));
   SCHK(hipMemsetAsync(d.red.counter, 0, 8 * sizeof(unsigned), sm));
   SCHK(hipMemsetAsync(d.shared, 0, sizeof(PcgShared), sm));
@@ -491,7 +505,7 @@ am_status algmortar_apply(am_handle h, const double* r, double* z, int32_t nrhs,
   HCHK(launch_permute_in(d.dperm, d.n, r, ld, d.r, nrhs, st));
   if (d.NL > 0) {
     HCHK(launch_bpart(d, d.r, nr, st));
-    HCHK(launch_iface_gemv(d, nr, st));
+    if (!d.fuse_eta) HCHK(launch_iface_gemv(d, nr, 0, 0, st));
   }
   HCHK(launch_local_sweep(d, d.r, d.z, d.eta, nr, 1, st));
   HCHK(launch_permute_out(d.dperm, d.n, d.z, z, ld, nrhs, st));
@@ -564,15 +578,22 @@ am_status algmortar_pcg(am_handle h, const double* b, double* x, int32_t nrhs, i
     }
     d.graph_nrhs = nr;
   }
+  // Chunks of kChunk iterations; the stop flag of chunk c is copied to pinned
+  // memory behind it and read while chunk c+1 already runs (a chunk launched
+  // after convergence only runs early-exit launches).
   const int max_chunks = maxit / kChunk + 2;
   for (int c = 0; c < max_chunks; ++c) {
     if (use_graph)
       HCHK(hipGraphLaunch(d.graph, st));
     else
       HCHK(run_chunk(d, nr, st));
-    HCHK(hipMemcpyAsync(d.h_flags, &d.shared->all_done, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    HCHK(hipStreamSynchronize(st));
-    if (d.h_flags[0]) break;
+    HCHK(hipMemcpyAsync(d.h_flags + (c & 1), &d.shared->all_done, sizeof(int32_t),
+                        hipMemcpyDeviceToHost, st));
+    HCHK(hipEventRecord(h->evf[c & 1], st));
+    if (c > 0) {
+      HCHK(hipEventSynchronize(h->evf[(c - 1) & 1]));
+      if (d.h_flags[(c - 1) & 1]) break;
+    }
   }
   HCHK(launch_permute_out(d.dperm, d.n, d.x, x, ld, nrhs, st));
   HCHK(hipEventRecord(h->ev1, st));
@@ -655,7 +676,7 @@ am_status algmortar_export_mbf(am_handle h, int64_t iface, int32_t sub, double* 
 
 am_status algmortar_time_kernel(am_handle h, int32_t kernel, int32_t nrhs, int32_t reps,
                                 double* avg_ms, double* bytes) {
-  if (!h || !avg_ms || !bytes || reps < 1 || kernel < 0 || kernel > 2 || nrhs < 1 ||
+  if (!h || !avg_ms || !bytes || reps < 1 || kernel < 0 || kernel > 4 || nrhs < 1 ||
       pow2_at_least(nrhs) > h->d.max_nrhs)
     return fail(h, AM_ERR_ARG, "bad argument");
   DeviceState& d = h->d;
@@ -675,6 +696,14 @@ am_status algmortar_time_kernel(am_handle h, int32_t kernel, int32_t nrhs, int32
     by += (double)d.NL * 8.0 * nr;
   } else if (kernel == 1) {
     by = (double)d.NL * d.NL * 8.0 + 3.0 * d.NL * 8.0 * nr;
+  } else if (kernel == 3) {
+    // ELL values and columns, z and p read, p and q written
+    by = (double)d.n * d.ell_w * 12.0 + 4.0 * d.n * 8.0 * nr;
+  } else if (kernel == 4) {
+    // x, p, r, q read, x and r written, MBFs read
+    by = 6.0 * d.n * 8.0 * nr;
+    for (int32_t s2 = 0; s2 < st.m; ++s2)
+      by += (double)(st.isub_ptr[s2 + 1] - st.isub_ptr[s2]) * (st.sub_ptr[s2 + 1] - st.sub_ptr[s2]) * 8.0;
   } else {
     for (int32_t s2 = 0; s2 < st.m; ++s2) {
       const double N = (double)(st.sub_ptr[s2 + 1] - st.sub_ptr[s2]);
@@ -685,9 +714,14 @@ am_status algmortar_time_kernel(am_handle h, int32_t kernel, int32_t nrhs, int32
   }
   HCHK(hipSetDevice(d.device));
   hipStream_t st0 = h->own;
+  if (kernel >= 3) {  // PCG kernels: run them on a live (not stopped) state
+    HCHK(launch_pcg_init(d, nr, 1e-300, 1 << 30, d.prec != AM_FP64 ? 1 : 0, st0));
+  }
   auto launch = [&]() -> hipError_t {
     if (kernel == 0) return launch_local_sweep(d, d.r, d.z, d.eta, nr, 1, st0);
-    if (kernel == 1) return launch_iface_gemv(d, nr, st0);
+    if (kernel == 1) return launch_iface_gemv(d, nr, 0, 0, st0);
+    if (kernel == 3) return launch_pcg_spmv(d, nr, 0, st0);
+    if (kernel == 4) return launch_pcg_update(d, nr, 0, st0);
     return launch_bpart(d, d.r, nr, st0);
   };
   HCHK(launch());  // warm-up

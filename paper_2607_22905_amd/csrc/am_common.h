@@ -22,6 +22,19 @@ __device__ __forceinline__ float readlane_f(float v, int lane) {
 }
 __device__ __forceinline__ double readlane(double v, int lane) { return readlane_d(v, lane); }
 __device__ __forceinline__ float readlane(float v, int lane) { return readlane_f(v, lane); }
+// The LLVM intrinsic behind v_writelane_b32 (no clang builtin exposes it).
+__device__ int am_writelane_i32(int v, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+// old with lane `lane` replaced by the uniform value v
+__device__ __forceinline__ double writelane(double v, int lane, double old) {
+  int2 a = __builtin_bit_cast(int2, v), o = __builtin_bit_cast(int2, old);
+  o.x = am_writelane_i32(a.x, lane, o.x);
+  o.y = am_writelane_i32(a.y, lane, o.y);
+  return __builtin_bit_cast(double, o);
+}
+__device__ __forceinline__ float writelane(float v, int lane, float old) {
+  return __builtin_bit_cast(float, am_writelane_i32(__builtin_bit_cast(int, v), lane,
+                                                    __builtin_bit_cast(int, old)));
+}
 
 // factor element loads (bf16 is stored as raw bits, widened to fp32)
 __device__ __forceinline__ double ld_fac(const double* p) { return *p; }
@@ -103,33 +116,47 @@ __device__ __forceinline__ bool all_done(const PcgShared* sh) {
 // Interface partial right-hand sides from r (not from pbar): for subdomain s
 // and slot q (basis function n = I_s[q]),
 //   bpart[s,q] = 1/4 * phat^(n)_s . r_s,
-// so that b_n = bpart[i, q_i] + bpart[j, q_j] = -sum_{e in E_n} a_e (pbar_k + pbar_l)/2.
+// stored at slot 2n + side (side 0 for the lower subdomain i, 1 for j), so that
+// b_n = bpart[2n] + bpart[2n+1] = -sum_{e in E_n} a_e (pbar_k + pbar_l)/2.
 // (A_s is symmetric and phat^(n)_s = A_s^{-1}(-B_s psi_n) = 4 A_s^{-1} w with
 // w_k = -sum a_e / 2 the weights of the edge average.)
 template <int NR>
 __device__ __forceinline__ void bpart_sub(int s, const int64_t* __restrict__ sub_ptr,
                                           const int64_t* __restrict__ isub_ptr,
                                           const int64_t* __restrict__ mbf_off,
-                                          const double* __restrict__ mbf, const double* r,
+                                          const double* __restrict__ mbf,
+                                          const int64_t* __restrict__ bdst, const double* r,
                                           double* bpart, double* lds) {
+  constexpr int QB = NR <= 2 ? 8 : (NR <= 4 ? 4 : (NR <= 8 ? 2 : 1));  // slots per round
   const int64_t base = sub_ptr[s];
   const int N = (int)(sub_ptr[s + 1] - base);
   const int64_t i0 = isub_ptr[s];
   const int ns = (int)(isub_ptr[s + 1] - i0);
   const double* P = mbf + mbf_off[s];
-  for (int q = 0; q < ns; ++q) {
-    double v[NR];
+  for (int q0 = 0; q0 < ns; q0 += QB) {
+    double v[QB * NR];
 #pragma unroll
-    for (int k = 0; k < NR; ++k) v[k] = 0.0;
+    for (int t = 0; t < QB * NR; ++t) v[t] = 0.0;
+#pragma unroll 2
     for (int row = threadIdx.x; row < N; row += blockDim.x) {
-      const double ph = P[(size_t)q * N + row];
+      double rv[NR];
 #pragma unroll
-      for (int k = 0; k < NR; ++k) v[k] = fma(ph, r[(size_t)(base + row) * NR + k], v[k]);
+      for (int k = 0; k < NR; ++k) rv[k] = r[(size_t)(base + row) * NR + k];
+#pragma unroll
+      for (int qq = 0; qq < QB; ++qq) {
+        const double ph = (q0 + qq < ns) ? P[(size_t)(q0 + qq) * N + row] : 0.0;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) v[qq * NR + k] = fma(ph, rv[k], v[qq * NR + k]);
+      }
     }
-    block_sum<NR>(v, lds);
+    block_sum<QB * NR>(v, lds);
     if (threadIdx.x == 0)
 #pragma unroll
-      for (int k = 0; k < NR; ++k) bpart[(size_t)(i0 + q) * NR + k] = 0.25 * v[k];
+      for (int qq = 0; qq < QB; ++qq)
+        if (q0 + qq < ns)
+#pragma unroll
+          for (int k = 0; k < NR; ++k)
+            bpart[(size_t)bdst[i0 + q0 + qq] * NR + k] = 0.25 * v[qq * NR + k];
   }
 }
 

@@ -18,7 +18,8 @@ constexpr int kTile = 64;     // dense interface-matrix tile
 
 // PCG scalars of one right-hand side, device resident.
 struct PcgScalars {
-  double rz;      // (r, z) of the current iterate
+  double rzv[2];  // (r, z), by iteration parity (written and read in different launches)
+  double rz;      // (r, z) of the last iteration (reporting)
   double pq;      // (p, A p)
   double alpha;
   double beta;
@@ -39,11 +40,17 @@ struct PcgShared {
   int32_t all_done;
 };
 
-// Scalar partial sums written by the reducing kernels; reduced by the last
-// workgroup of each launch in a fixed order (deterministic).
+// Per-block partial sums of the PCG dots.  The kernel that needs a scalar
+// folds the producer's partials itself, in block order, identically in every
+// workgroup (deterministic, no fences or atomics); workgroup 0 stores the
+// scalars for later launches.
 struct Reduce {
-  double* partial = nullptr;    // [max_blocks * kMaxNRHS * 2]
-  unsigned* counter = nullptr;  // one counter per reducing kernel kind
+  double* pa = nullptr;         // (p, Ap) per SpMV block          [spmv_blocks][NR]
+  double* pb = nullptr;         // ||r||^2 per subdomain            [m][NR]
+  double* pd = nullptr;         // (r, z), (q, z) per subdomain     [m][2 NR]
+  double* partial = nullptr;    // true-residual partials
+  unsigned* counter = nullptr;
+  int spmv_blocks = 0;
   int max_blocks = 0;
 };
 
@@ -54,6 +61,7 @@ struct DeviceState {
   int32_t m = 0;
   int64_t NL = 0, NE = 0;
   int32_t ldS = 0;  // padded interface dimension (multiple of kTile)
+  int32_t fuse_eta = 0;  // local kernel computes its own rows of eta = S^{-1} b
   int32_t max_nrhs = 1;
 
   // device ordering and permuted matrix
@@ -94,7 +102,7 @@ struct DeviceState {
   int32_t* e_kloc = nullptr;     // [NE] local row of k in subdomain i
   int32_t* e_lloc = nullptr;     // [NE] local row of l in subdomain j
   double* e_a = nullptr;         // [NE]
-  int64_t* bidx = nullptr;       // [2 NL] index into the (subdomain, slot) partials
+  int64_t* bdst = nullptr;       // [2 NL] (subdomain, slot) pair -> slot 2n + side of bpart
   double* S = nullptr;           // [ldS * ldS] symmetrised interface matrix
   double* Sinv = nullptr;        // [ldS * ldS]
 
@@ -104,7 +112,7 @@ struct DeviceState {
   double* z = nullptr;
   double* p[2] = {nullptr, nullptr};
   double* q = nullptr;
-  double* bpart = nullptr;  // [2 NL][nrhs]
+  double* bpart = nullptr;  // [2 NL][nrhs], slot 2n + side
   double* eta = nullptr;    // [ldS][nrhs]
   PcgScalars* sc = nullptr; // [kMaxNRHS]
   PcgShared* shared = nullptr;
@@ -130,7 +138,9 @@ hipError_t launch_bpart(DeviceState& d, const double* r, int nrhs, hipStream_t s
 // ---- launchers (kernels_iface.hip) ----
 hipError_t launch_assemble_S(DeviceState& d, hipStream_t s);
 hipError_t dense_cholesky_inverse(DeviceState& d, double* L, double* Linv, hipStream_t s);
-hipError_t launch_iface_gemv(DeviceState& d, int nrhs, hipStream_t s);
+// eta = S^{-1} b; in PCG mode (pcg != 0) the launch first applies the stop
+// test to the ||r||^2 partials (init: records ||b||^2)
+hipError_t launch_iface_gemv(DeviceState& d, int nrhs, int pcg, int init, hipStream_t s);
 
 // ---- launchers (kernels_pcg.hip) ----
 hipError_t launch_permute_in(const int32_t* dperm, int64_t n, const double* src, int64_t ld,
@@ -142,6 +152,8 @@ hipError_t launch_pcg_init(DeviceState& d, int nrhs, double tol, int maxit, int 
                            hipStream_t s);
 hipError_t launch_pcg_iteration(DeviceState& d, int nrhs, int parity, hipStream_t s);
 hipError_t launch_pcg_start(DeviceState& d, int nrhs, hipStream_t s);
+hipError_t launch_pcg_spmv(DeviceState& d, int nrhs, int parity, hipStream_t s);
+hipError_t launch_pcg_update(DeviceState& d, int nrhs, int parity, hipStream_t s);
 hipError_t launch_true_residual(DeviceState& d, const double* bperm, int nrhs, double* out2,
                                 hipStream_t s);
 

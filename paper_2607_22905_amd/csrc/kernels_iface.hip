@@ -7,6 +7,8 @@
 //
 // Dense tiles are 64 x 64, row-major with leading dimension ldS (a multiple
 // of 64); rows/columns beyond N_Lambda hold the identity.
+#include <algorithm>
+
 #include "am_common.h"
 
 namespace am {
@@ -257,52 +259,95 @@ __global__ __launch_bounds__(256) void k_lauum(const double* Li, double* Sinv, i
 }
 
 // ---------------------------------------------------------------------------
-// eta = S^{-1} b, b_m = bpart[bidx[2m]] + bpart[bidx[2m+1]].  Each wave owns
-// ROWS rows of S^{-1}; b is staged through LDS in chunks.
-template <int NR, int ROWS>
+// eta = S^{-1} b, b_m = bpart[2m] + bpart[2m+1].  Each wave owns one row of
+// S^{-1}; b is staged through LDS in chunks of CH.  In PCG mode every
+// workgroup first folds the ||r||^2 partials of the update launch (same order
+// in every workgroup) and applies the stop test ||r|| <= tol ||b||;
+// workgroup 0 stores the outcome and a stopped solve skips the product.  The
+// first chunk of b and of the row are loaded before that fold, so a launch
+// whose interface fits one chunk costs one memory round trip.
+template <int NR>
 __global__ __launch_bounds__(256) void k_iface_gemv(int NL, int ldS, const double* __restrict__ Sinv,
-                                                    const double* __restrict__ bpart,
-                                                    const int64_t* __restrict__ bidx, double* eta,
-                                                    const PcgShared* sh, int check_done) {
-  if (check_done && all_done(sh)) return;
-  constexpr int CH = NR <= 2 ? 1024 : (NR <= 4 ? 512 : 256);
+                                                    const double* __restrict__ bpart, double* eta,
+                                                    int pcg, int init, const double* __restrict__ pb,
+                                                    int npb, PcgScalars* sc, PcgShared* sh) {
+  constexpr int CH = NR <= 2 ? 2048 : (NR <= 4 ? 1024 : 512);
+  constexpr int RV = CH / 64;            // row values per lane per chunk
+  constexpr int BV = (CH * NR) / 256;    // staged b values per thread per chunk
   __shared__ double bs[CH * NR];
+  __shared__ double lds[4 * NR];
+  if (pcg && !init && all_done(sh)) return;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int n0 = (blockIdx.x * 4 + w) * ROWS;
-  double acc[ROWS][NR];
+  const int n = blockIdx.x * 4 + w;
+  const double* row = Sinv + (size_t)min(n, max(NL - 1, 0)) * ldS;
+  double acc[NR];
 #pragma unroll
-  for (int r = 0; r < ROWS; ++r)
+  for (int k = 0; k < NR; ++k) acc[k] = 0.0;
+  for (int m0 = 0; m0 < NL || (m0 == 0 && pcg); m0 += CH) {
+    const int cnt = max(0, min(CH, NL - m0));
+    double bv[BV], sv[RV];
 #pragma unroll
-    for (int k = 0; k < NR; ++k) acc[r][k] = 0.0;
-  for (int m0 = 0; m0 < NL; m0 += CH) {
-    const int cnt = min(CH, NL - m0);
-    for (int t = threadIdx.x; t < cnt * NR; t += blockDim.x) {
+    for (int u = 0; u < BV; ++u) {
+      const int t = threadIdx.x + 256 * u;
       const int m = m0 + t / NR, k = t % NR;
-      bs[t] = bpart[(size_t)bidx[2 * m] * NR + k] + bpart[(size_t)bidx[2 * m + 1] * NR + k];
+      bv[u] = (t < cnt * NR) ? bpart[(size_t)(2 * m) * NR + k] + bpart[(size_t)(2 * m + 1) * NR + k] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < RV; ++u) {
+      const int mm = lane + 64 * u;
+      sv[u] = (mm < cnt && n < NL) ? row[m0 + mm] : 0.0;
+    }
+    if (pcg && m0 == 0) {
+      double rr[NR];
+      reduce_partials<NR>(rr, pb, (unsigned)npb, lds);
+      int alld = 1;
+      for (int k = 0; k < sh->nrhs; ++k) {
+        const PcgScalars S = sc[k];
+        int done = S.done, conv = S.conv, status = S.status;
+        double bb = S.bb;
+        if (!done) {
+          if (init) {
+            bb = rr[k];
+            if (bb == 0.0) done = conv = 1;
+          } else if (rr[k] <= S.tol2 * S.bb) {
+            done = conv = 1;
+          } else if (S.it >= sh->maxit) {
+            done = 1;
+            status = AM_ERR_NO_CONVERGENCE;
+          }
+        }
+        alld &= done;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+          sc[k].rr = rr[k];
+          sc[k].bb = bb;
+          sc[k].done = done;
+          sc[k].conv = conv;
+          sc[k].status = status;
+        }
+      }
+      if (blockIdx.x == 0 && threadIdx.x == 0) sh->all_done = alld;
+      if (alld) return;
+    }
+    if (cnt == 0) break;
+#pragma unroll
+    for (int u = 0; u < BV; ++u) {
+      const int t = threadIdx.x + 256 * u;
+      if (t < cnt * NR) bs[t] = bv[u];
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < ROWS; ++r) {
-      const int n = n0 + r;
-      if (n < NL) {
-        const double* row = Sinv + (size_t)n * ldS + m0;
-        for (int mm = lane; mm < cnt; mm += 64) {
-          const double sv = row[mm];
+    for (int u = 0; u < RV; ++u) {
+      const int mm = lane + 64 * u;
+      if (mm < cnt)
 #pragma unroll
-          for (int k = 0; k < NR; ++k) acc[r][k] = fma(sv, bs[mm * NR + k], acc[r][k]);
-        }
-      }
+        for (int k = 0; k < NR; ++k) acc[k] = fma(sv[u], bs[mm * NR + k], acc[k]);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int r = 0; r < ROWS; ++r) {
-    const int n = n0 + r;
-#pragma unroll
-    for (int k = 0; k < NR; ++k) {
-      const double v = wave_sum(acc[r][k]);
-      if (lane == 0 && n < NL) eta[(size_t)n * NR + k] = v;
-    }
+  for (int k = 0; k < NR; ++k) {
+    const double v = wave_sum(acc[k]);
+    if (lane == 0 && n < NL) eta[(size_t)n * NR + k] = v;
   }
 }
 
@@ -342,23 +387,20 @@ hipError_t dense_cholesky_inverse(DeviceState& d, double* L, double* Li, hipStre
 }
 
 template <int NR>
-static void gemv_t(DeviceState& d, hipStream_t st, int check) {
-  constexpr int ROWS = 1;
-  const unsigned nb = (unsigned)((d.NL + 4 * ROWS - 1) / (4 * ROWS));
-  hipLaunchKernelGGL((k_iface_gemv<NR, ROWS>), dim3(nb), dim3(256), 0, st, (int)d.NL, d.ldS,
-                     d.Sinv, d.bpart, d.bidx, d.eta, d.shared, check);
+static void gemv_t(DeviceState& d, hipStream_t st, int pcg, int init) {
+  const unsigned nb = (unsigned)std::max<int64_t>(1, (d.NL + 3) / 4);
+  hipLaunchKernelGGL((k_iface_gemv<NR>), dim3(nb), dim3(256), 0, st, (int)d.NL, d.ldS, d.Sinv,
+                     d.bpart, d.eta, pcg, init, d.red.pb, d.m, d.sc, d.shared);
 }
 
-hipError_t launch_iface_gemv(DeviceState& d, int nrhs, hipStream_t st) {
-  if (d.NL == 0) return hipSuccess;
-  const int check = nrhs < 0 ? 1 : 0;
-  const int nr = nrhs < 0 ? -nrhs : nrhs;
+hipError_t launch_iface_gemv(DeviceState& d, int nr, int pcg, int init, hipStream_t st) {
+  if (d.NL == 0 && !pcg) return hipSuccess;
   switch (nr) {
-    case 1: gemv_t<1>(d, st, check); break;
-    case 2: gemv_t<2>(d, st, check); break;
-    case 4: gemv_t<4>(d, st, check); break;
-    case 8: gemv_t<8>(d, st, check); break;
-    case 16: gemv_t<16>(d, st, check); break;
+    case 1: gemv_t<1>(d, st, pcg, init); break;
+    case 2: gemv_t<2>(d, st, pcg, init); break;
+    case 4: gemv_t<4>(d, st, pcg, init); break;
+    case 8: gemv_t<8>(d, st, pcg, init); break;
+    case 16: gemv_t<16>(d, st, pcg, init); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -13,8 +13,11 @@
 // so that both the forward sweep (column j) and the backward sweep (row j)
 // read one contiguous WP-vector per step: lane t of the wave owns slots
 // t, t+64, ... and each step is one coalesced load, a broadcast of the pivot
-// (readlane) and one FMA per slot.  invd[j] = 1/L_jj.  Padding rows have a
-// zero factor and invd = 1.
+// (readlane), one FMA per slot and one writelane.  The factor is kept in unit-diagonal form
+// A_i = Lt D Lt^T (Lt = L diag(1/L_jj), D = diag(L_jj^2)): the sweeps then
+// need no division per step; dinv[j] = 1/L_jj^2 scales w = Lt^{-1} r once
+// per row between the two sweeps.  Padding rows have a zero factor and
+// dinv = 1.
 #include "am_common.h"
 
 namespace am {
@@ -22,13 +25,30 @@ namespace am {
 template <typename FT> struct AccT { using T = float; };
 template <> struct AccT<double> { using T = double; };
 
-// prefetch distance (steps) of the rolling register ring; the sweeps run in
-// fully unrolled chunks of RING steps (RING divides 64)
+// prefetch distance (steps) of the rolling register ring (RING divides 64);
+// each block of 64 steps is fully unrolled so that the only loop back-edge
+// (where the compiler merges outstanding-load counts) is once per block
 #ifndef ALGMORTAR_RING1
 #define ALGMORTAR_RING1 32
 #endif
+// One drain of the vector-memory counter before a sweep's main loop, so that
+// the loads issued before the loop never force a full drain inside it.
+__device__ __forceinline__ void wait_all_loads() {
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0); expcnt, lgkmcnt untouched
+}
+// A copy of v the compiler cannot see through, so that per-step compares
+// against it are evaluated in the step (and not kept live as 64 masks).
+__device__ __forceinline__ int opaque(int v) {
+  int r;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "v"(v));
+  return r;
+}
+// Keep each step's refill load where it is written (issued right after the
+// slot is consumed): the scheduler may not move instructions across.
+__device__ __forceinline__ void step_fence() { __builtin_amdgcn_sched_barrier(0); }
+
 template <int C, int NR> struct Ring {
-  static constexpr int v = (C * NR <= 1) ? ALGMORTAR_RING1 : (C * NR <= 2) ? 32 : (C * NR <= 8) ? 16 : 8;
+  static constexpr int v = (C * NR <= 1) ? ALGMORTAR_RING1 : (C * NR <= 2) ? 32 : (C * NR <= 8) ? 16 : 4;
 };
 
 // ---------------------------------------------------------------------------
@@ -85,15 +105,16 @@ __global__ __launch_bounds__(256) void k_band_factor(
     const double inv = bad ? 1.0 : 1.0 / sqrt(d);
     if (tid == 0) {
       if (bad && atomicCAS(fail, -1, s) == -1) fail[1] = j;
-      iv[j] = (IT)inv;
+      iv[j] = (IT)(inv * inv);
     }
     for (int t = tid; t < WP; t += blockDim.x) {
       const int row = j + 1 + t;
       double l = 0.0;
-      if (row < N) l = B[(row % WN) * WN + sj] * inv;
+      if (row < N) l = B[(row % WN) * WN + sj] * inv;  // L[row, j]
       lcol[row % WN] = l;
-      st_fac(lc + (size_t)j * WP + (row % WP), l);
-      if (row < N) st_fac(lr + (size_t)row * WP + (j % WP), l);
+      const double lt = l * inv;                        // Lt[row, j] = L[row, j] / L[j, j]
+      st_fac(lc + (size_t)j * WP + (row % WP), lt);
+      if (row < N) st_fac(lr + (size_t)row * WP + (j % WP), lt);
     }
     __syncthreads();
     const int nu = j + WP + 1;
@@ -114,11 +135,19 @@ __global__ __launch_bounds__(256) void k_band_factor(
 }
 
 // ---------------------------------------------------------------------------
-// Forward sweep L y = r.  Window before step j: rows j..j+WP-1; the pivot of
-// step j sits in slot j % WP, whose lane then takes row j+WP.
+// Forward sweep Lt w = r, then v = dinv * w written to yout.  Window before
+// step j: rows j..j+WP-1, row i held by lane (i % WP) % 64 in accumulator
+// (i % WP) / 64.  At step j the pivot w_j is broadcast from lane t = j % 64
+// (readlane), the owner lane's slot switches to row j+WP (its accumulator is
+// replaced by r[j+WP]), every lane applies acc -= Lt[row, j] * w_j (one FMA)
+// and w_j is recorded in lane t (writelane).  The owner's test is a compare
+// against a per-block lane index, so no per-step masks are kept live.
+// Per-block values consumed at a block's start (the rows entering the window)
+// are loaded one block ahead, so no wait on them drains the factor prefetch
+// ring.
 template <typename FT, int C, int NR>
 __device__ __forceinline__ void fwd_sweep(const int N, const int NP, const FT* __restrict__ lc,
-                                          const typename AccT<FT>::T* __restrict__ iv,
+                                          const typename AccT<FT>::T* __restrict__ dv,
                                           const double* rin, double* yout) {
   using AT = typename AccT<FT>::T;
   constexpr int WP = 64 * C;
@@ -133,23 +162,32 @@ __device__ __forceinline__ void fwd_sweep(const int N, const int NP, const FT* _
   }
   AT buf[RING][C];
 #pragma unroll
-  for (int t = 0; t < RING; ++t)
+  for (int t = 0; t < RING; ++t) {
+    const FT* colp = lc + (size_t)min(t, NP - 1) * WP;
 #pragma unroll
-    for (int c = 0; c < C; ++c)
-      buf[t][c] = ld_fac(lc + (size_t)min(t, NP - 1) * WP + 64 * c + lane);
+    for (int c = 0; c < C; ++c) buf[t][c] = ld_fac(colp + 64 * c + lane);
+  }
+  AT rn[NR];
+  {
+    const int nrow = WP + lane;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) rn[k] = nrow < N ? (AT)rin[(size_t)nrow * NR + k] : (AT)0;
+  }
+  wait_all_loads();
 
   for (int b = 0; b < NP / 64; ++b) {
     const int j0 = 64 * b;
     const int cb = b % C;
-    AT rn[NR];
-    const int nrow = j0 + WP + lane;
+    AT rnx[NR];
+    const int nrow = j0 + 64 + WP + lane;
 #pragma unroll
-    for (int k = 0; k < NR; ++k) rn[k] = nrow < N ? (AT)rin[(size_t)nrow * NR + k] : (AT)0;
-    const AT ivl = iv[j0 + lane];
+    for (int k = 0; k < NR; ++k) rnx[k] = nrow < N ? (AT)rin[(size_t)nrow * NR + k] : (AT)0;
+    const AT dvl = dv[j0 + lane];
+    const int lane_j = opaque(j0 + lane);
     AT yl[NR];
 #pragma unroll
     for (int k = 0; k < NR; ++k) yl[k] = (AT)0;
-#pragma unroll 1
+#pragma unroll
     for (int ch = 0; ch < 64; ch += RING) {
 #pragma unroll
       for (int tt = 0; tt < RING; ++tt) {
@@ -158,47 +196,47 @@ __device__ __forceinline__ void fwd_sweep(const int N, const int NP, const FT* _
         AT l[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) l[c] = buf[tt][c];
-        const int jn = min(j + RING, NP - 1);
+        const FT* colp = lc + (size_t)min(j + RING, NP - 1) * WP;
 #pragma unroll
-        for (int c = 0; c < C; ++c) buf[tt][c] = ld_fac(lc + (size_t)jn * WP + 64 * c + lane);
-        const AT inv = readlane(ivl, t);
+        for (int c = 0; c < C; ++c) buf[tt][c] = ld_fac(colp + 64 * c + lane);
         AT y[NR];
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
           AT piv = acc[0][k];
 #pragma unroll
           for (int c = 1; c < C; ++c) piv = (cb == c) ? acc[c][k] : piv;
-          y[k] = readlane(piv, t) * inv;
+          y[k] = readlane(piv, t);
         }
-        const bool own = (lane == t);
+        const bool own = (lane_j == j);
 #pragma unroll
         for (int c = 0; c < C; ++c) {
           const bool take = own && (c == cb);
 #pragma unroll
-          for (int k = 0; k < NR; ++k) {
-            const AT a = take ? rn[k] : acc[c][k];
-            acc[c][k] = fma(-l[c], y[k], a);
-          }
+          for (int k = 0; k < NR; ++k) acc[c][k] = fma(-l[c], y[k], take ? rn[k] : acc[c][k]);
         }
 #pragma unroll
-        for (int k = 0; k < NR; ++k) yl[k] = own ? y[k] : yl[k];
+        for (int k = 0; k < NR; ++k) yl[k] = writelane(y[k], t, yl[k]);
+        step_fence();
       }
     }
     const int row = j0 + lane;
     if (row < N)
 #pragma unroll
-      for (int k = 0; k < NR; ++k) yout[(size_t)row * NR + k] = (double)yl[k];
+      for (int k = 0; k < NR; ++k) yout[(size_t)row * NR + k] = (double)(yl[k] * dvl);
+#pragma unroll
+    for (int k = 0; k < NR; ++k) rn[k] = rnx[k];
   }
 }
 
-// Backward sweep L^T x = y (y read from and x written to yx).  Window before
-// step j (descending): rows j-WP+1..j; slot j % WP then takes row j-WP.
-// After each block of 64 steps, lane t holds x of row j0+t and calls
-// epi(row, x[NR]).
-template <typename FT, int C, int NR, class Epi>
+// Backward sweep Lt^T x = v (v read from and x written to yx).  Window before
+// step j (descending): rows j-WP+1..j; the owner slot j % WP then takes row
+// j-WP.  pre(row) is
+// called at the start of each block of 64 steps (to issue the loads its
+// epilogue needs early), post(row, x[NR]) at its end, when lane t holds x of
+// row j0+t.
+template <typename FT, int C, int NR, class Pre, class Post>
 __device__ __forceinline__ void bwd_sweep(const int N, const int NP, const FT* __restrict__ lr,
-                                          const typename AccT<FT>::T* __restrict__ iv,
-                                          const double* yx, Epi& epi) {
+                                          const double* yx, Pre& pre, Post& post) {
   using AT = typename AccT<FT>::T;
   constexpr int WP = 64 * C;
   constexpr int RING = Ring<C, NR>::v;
@@ -213,91 +251,149 @@ __device__ __forceinline__ void bwd_sweep(const int N, const int NP, const FT* _
     for (int k = 0; k < NR; ++k)
       acc[c][k] = (row >= 0 && row < N) ? (AT)yx[(size_t)row * NR + k] : (AT)0;
   }
-  // ring slot u holds the column consumed u steps (mod RING) after the start
+  // ring slot u holds the row consumed u steps (mod RING) after the start
   AT buf[RING][C];
 #pragma unroll
-  for (int u = 0; u < RING; ++u)
+  for (int u = 0; u < RING; ++u) {
+    const FT* rowp = lr + (size_t)max(NP - 1 - u, 0) * WP;
 #pragma unroll
-    for (int c = 0; c < C; ++c)
-      buf[u][c] = ld_fac(lr + (size_t)max(NP - 1 - u, 0) * WP + 64 * c + lane);
-
-  for (int b = NP / 64 - 1; b >= 0; --b) {
-    const int j0 = 64 * b;
-    const int cb = b % C;
-    AT rn[NR];
-    const int nrow = j0 + lane - WP;
+    for (int c = 0; c < C; ++c) buf[u][c] = ld_fac(rowp + 64 * c + lane);
+  }
+  const int nb = NP / 64;
+  AT rn[NR];
+  {
+    const int nrow = 64 * (nb - 1) + lane - WP;
 #pragma unroll
     for (int k = 0; k < NR; ++k) rn[k] = nrow >= 0 ? (AT)yx[(size_t)nrow * NR + k] : (AT)0;
-    const AT ivl = iv[j0 + lane];
+  }
+  wait_all_loads();
+
+  for (int b = nb - 1; b >= 0; --b) {
+    const int j0 = 64 * b;
+    const int cb = b % C;
+    AT rnx[NR];
+    const int nrow = j0 - 64 + lane - WP;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) rnx[k] = nrow >= 0 ? (AT)yx[(size_t)nrow * NR + k] : (AT)0;
+    pre(j0 + lane);
+    const int lane_j = opaque(j0 + lane);
     AT xl[NR];
 #pragma unroll
     for (int k = 0; k < NR; ++k) xl[k] = (AT)0;
-#pragma unroll 1
+#pragma unroll
     for (int ch = 64 - RING; ch >= 0; ch -= RING) {
 #pragma unroll
       for (int tt = RING - 1; tt >= 0; --tt) {
         const int t = ch + tt;
         const int j = j0 + t;
-        constexpr int dummy = 0;
-        (void)dummy;
         const int su = RING - 1 - tt;
         AT l[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) l[c] = buf[su][c];
-        const int jn = max(j - RING, 0);
+        const FT* rowp = lr + (size_t)max(j - RING, 0) * WP;
 #pragma unroll
-        for (int c = 0; c < C; ++c) buf[su][c] = ld_fac(lr + (size_t)jn * WP + 64 * c + lane);
-        const AT inv = readlane(ivl, t);
+        for (int c = 0; c < C; ++c) buf[su][c] = ld_fac(rowp + 64 * c + lane);
         AT x[NR];
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
           AT piv = acc[0][k];
 #pragma unroll
           for (int c = 1; c < C; ++c) piv = (cb == c) ? acc[c][k] : piv;
-          x[k] = readlane(piv, t) * inv;
+          x[k] = readlane(piv, t);
         }
-        const bool own = (lane == t);
+        const bool own = (lane_j == j);
 #pragma unroll
         for (int c = 0; c < C; ++c) {
           const bool take = own && (c == cb);
 #pragma unroll
-          for (int k = 0; k < NR; ++k) {
-            const AT a = take ? rn[k] : acc[c][k];
-            acc[c][k] = fma(-l[c], x[k], a);
-          }
+          for (int k = 0; k < NR; ++k) acc[c][k] = fma(-l[c], x[k], take ? rn[k] : acc[c][k]);
         }
 #pragma unroll
-        for (int k = 0; k < NR; ++k) xl[k] = own ? x[k] : xl[k];
+        for (int k = 0; k < NR; ++k) xl[k] = writelane(x[k], t, xl[k]);
+        step_fence();
       }
     }
     double xd[NR];
 #pragma unroll
     for (int k = 0; k < NR; ++k) xd[k] = (double)xl[k];
-    epi(j0 + lane, xd);
+    post(j0 + lane, xd);
+#pragma unroll
+    for (int k = 0; k < NR; ++k) rn[k] = rnx[k];
   }
 }
 
 // ---------------------------------------------------------------------------
-// Local solve / apply kernel, one wave per subdomain.
+// Local solve / apply kernel, one subdomain per workgroup of two waves.
 //   mode 0: out = A_i^{-1} r                          (local particular solution)
 //   mode 1: out = A_i^{-1} r + sum_q eta_q phat^(q)    (preconditioner apply)
-//   mode 2: mode 1 plus (r, z) and (q, z) for PCG; the last block updates beta
+//   mode 2: mode 1 plus this block's (r, z) and (q, z) partial sums for PCG
+// Wave 0 runs the two band sweeps.  Wave 1 gathers eta for the subdomain's
+// basis functions while wave 0 runs the forward sweep: from the global eta
+// (computed by the interface GEMV) or, when fuse_eta is set, as the
+// subdomain's own rows of eta = S^{-1} b (so no separate interface launch is
+// needed); in PCG mode with fuse_eta it also folds the ||r||^2 partials and
+// applies the stop test ||r|| <= tol ||b|| (workgroup 0 stores the outcome).
 constexpr int kMaxNiLds = 128;
+constexpr int kPreQ = 8;  // MBF columns whose values are fetched a block ahead
+constexpr int kEtaChunk = 24;  // interface columns per lane per chunk of the fused rows
+
+template <int NR>
+__device__ __forceinline__ bool stop_test(const double* __restrict__ pb, int npb, int init,
+                                          PcgScalars* sc, PcgShared* sh) {
+  // one wave: fold the ||r||^2 partials in block order (same order in every workgroup)
+  const int lane = threadIdx.x & 63;
+  double rr[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) rr[k] = 0.0;
+  for (int b = lane; b < npb; b += 64)
+#pragma unroll
+    for (int k = 0; k < NR; ++k) rr[k] += pb[(size_t)b * NR + k];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) rr[k] = wave_sum(rr[k]);
+  int alld = 1;
+  for (int k = 0; k < sh->nrhs; ++k) {
+    const PcgScalars S = sc[k];
+    int done = S.done, conv = S.conv, status = S.status;
+    double bb = S.bb;
+    if (!done) {
+      if (init) {
+        bb = rr[k];
+        if (bb == 0.0) done = conv = 1;
+      } else if (rr[k] <= S.tol2 * S.bb) {
+        done = conv = 1;
+      } else if (S.it >= sh->maxit) {
+        done = 1;
+        status = AM_ERR_NO_CONVERGENCE;
+      }
+    }
+    alld &= done;
+    if (blockIdx.x == 0 && lane == 0) {
+      sc[k].rr = rr[k];
+      sc[k].bb = bb;
+      sc[k].done = done;
+      sc[k].conv = conv;
+      sc[k].status = status;
+    }
+  }
+  if (blockIdx.x == 0 && lane == 0) sh->all_done = alld;
+  return alld != 0;
+}
 
 template <typename FT, int C, int NR>
-__global__ __launch_bounds__(64) void k_local(
+__global__ __launch_bounds__(128) void k_local(
     const int32_t* __restrict__ subs, const int64_t* __restrict__ sub_ptr,
     const int64_t* __restrict__ roff, const int64_t* __restrict__ fac_off,
     const FT* __restrict__ Lc, const FT* __restrict__ Lr,
-    const typename AccT<FT>::T* __restrict__ invd, const double* rin, double* out, int mode,
+    const typename AccT<FT>::T* __restrict__ dinv, const double* rin, double* out, int mode,
     const int64_t* __restrict__ isub_ptr, const int32_t* __restrict__ isub_list,
     const int64_t* __restrict__ mbf_off, const double* __restrict__ mbf,
-    const double* __restrict__ eta, const double* __restrict__ qv, double* partial,
-    unsigned* counter, unsigned blk_off, unsigned nblk_total, PcgScalars* sc, PcgShared* sh,
-    int init) {
+    const double* __restrict__ eta, const double* __restrict__ qv, double* __restrict__ partial,
+    unsigned blk_off, int fuse_eta, const double* __restrict__ Sinv, int NL, int ldS,
+    const double* __restrict__ bpart, const double* __restrict__ pb, int npb, int init,
+    PcgScalars* sc, PcgShared* sh) {
   if (mode == 2 && all_done(sh)) return;
   __shared__ double eta_s[kMaxNiLds * NR];
-  __shared__ double red[2 * NR];
+  __shared__ int stop_s;
   const int s = subs[blockIdx.x];
   const int64_t base = sub_ptr[s];
   const int N = (int)(sub_ptr[s + 1] - base);
@@ -305,96 +401,121 @@ __global__ __launch_bounds__(64) void k_local(
   const int NP = (int)(roff[s + 1] - ro);
   const FT* lc = Lc + fac_off[s];
   const FT* lr = Lr + fac_off[s];
-  const auto* iv = invd + ro;
-  const int lane = threadIdx.x;
+  const auto* dv = dinv + ro;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
   const int64_t i0 = isub_ptr[s];
-  const int ns = (int)(isub_ptr[s + 1] - i0);
+  const int ns = mode >= 1 ? (int)(isub_ptr[s + 1] - i0) : 0;
   const double* P = mbf + mbf_off[s];
-  if (mode >= 1)
-    for (int t = lane; t < ns * NR; t += 64)
-      eta_s[t] = eta[(size_t)isub_list[i0 + t / NR] * NR + (t % NR)];
 
-  fwd_sweep<FT, C, NR>(N, NP, lc, iv, rin + base * NR, out + base * NR);
+  if (wave == 0) {
+    fwd_sweep<FT, C, NR>(N, NP, lc, dv, rin + base * NR, out + base * NR);
+  } else {
+    int stop = 0;
+    if (mode == 2 && fuse_eta) stop = stop_test<NR>(pb, npb, init, sc, sh) ? 1 : 0;
+    if (lane == 0) stop_s = stop;
+    if (!stop && ns > 0) {
+      if (!fuse_eta) {
+        for (int t = lane; t < ns * NR; t += 64)
+          eta_s[t] = eta[(size_t)isub_list[i0 + t / NR] * NR + (t % NR)];
+      } else {
+        // rows I_s[q] of S^{-1} times b, b_m = bpart[2m] + bpart[2m+1]
+        for (int q = 0; q < ns; ++q)
+          if (lane == 0)
+#pragma unroll
+            for (int k = 0; k < NR; ++k) eta_s[q * NR + k] = 0.0;
+        for (int m0 = 0; m0 < NL; m0 += 64 * kEtaChunk) {
+          double bv[kEtaChunk][NR];
+#pragma unroll
+          for (int u = 0; u < kEtaChunk; ++u) {
+            const int m = m0 + lane + 64 * u;
+#pragma unroll
+            for (int k = 0; k < NR; ++k)
+              bv[u][k] = m < NL ? bpart[(size_t)(2 * m) * NR + k] + bpart[(size_t)(2 * m + 1) * NR + k] : 0.0;
+          }
+          for (int q = 0; q < ns; ++q) {
+            const double* row = Sinv + (size_t)isub_list[i0 + q] * ldS;
+            double a[NR];
+#pragma unroll
+            for (int k = 0; k < NR; ++k) a[k] = 0.0;
+#pragma unroll
+            for (int u = 0; u < kEtaChunk; ++u) {
+              const int m = m0 + lane + 64 * u;
+              const double sv = m < NL ? row[m] : 0.0;
+#pragma unroll
+              for (int k = 0; k < NR; ++k) a[k] = fma(sv, bv[u][k], a[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < NR; ++k) {
+              const double t = wave_sum(a[k]);
+              if (lane == 0) eta_s[q * NR + k] += t;
+            }
+          }
+        }
+      }
+    }
+  }
   __syncthreads();
+  if (stop_s) return;
+  if (wave != 0) return;
 
   double rz[NR], qz[NR];
 #pragma unroll
   for (int k = 0; k < NR; ++k) rz[k] = qz[k] = 0.0;
   double* o = out + base * NR;
   const double* rr = rin + base * NR;
-  const double* qq = qv ? qv + base * NR : nullptr;
-  auto epi = [&](int row, double (&x)[NR]) {
+  const double* qq = qv + base * NR;
+  double ph[kPreQ], rpre[NR], qpre[NR];
+#pragma unroll
+  for (int q = 0; q < kPreQ; ++q) ph[q] = 0.0;
+#pragma unroll
+  for (int k = 0; k < NR; ++k) rpre[k] = qpre[k] = 0.0;
+  const int npre = min(ns, kPreQ);
+  auto pre = [&](int row) {
     if (row >= N) return;
-    if (mode >= 1)
-      for (int q = 0; q < ns; ++q) {
-        const double ph = P[(size_t)q * N + row];
 #pragma unroll
-        for (int k = 0; k < NR; ++k) x[k] = fma(ph, eta_s[q * NR + k], x[k]);
-      }
-#pragma unroll
-    for (int k = 0; k < NR; ++k) o[(size_t)row * NR + k] = x[k];
-    if (mode == 2) {
+    for (int q = 0; q < kPreQ; ++q)
+      if (q < npre) ph[q] = P[(size_t)q * N + row];
+    if (mode == 2)
 #pragma unroll
       for (int k = 0; k < NR; ++k) {
-        rz[k] = fma(rr[(size_t)row * NR + k], x[k], rz[k]);
-        qz[k] = fma(qq[(size_t)row * NR + k], x[k], qz[k]);
+        rpre[k] = rr[(size_t)row * NR + k];
+        qpre[k] = qq[(size_t)row * NR + k];
       }
-    }
   };
-  bwd_sweep<FT, C, NR>(N, NP, lr, iv, out + base * NR, epi);
+  auto post = [&](int row, double (&x)[NR]) {
+    if (row >= N) return;
+#pragma unroll
+    for (int q = 0; q < kPreQ; ++q)
+      if (q < npre)
+#pragma unroll
+        for (int k = 0; k < NR; ++k) x[k] = fma(ph[q], eta_s[q * NR + k], x[k]);
+    for (int q = kPreQ; q < ns; ++q) {
+      const double v = P[(size_t)q * N + row];
+#pragma unroll
+      for (int k = 0; k < NR; ++k) x[k] = fma(v, eta_s[q * NR + k], x[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < NR; ++k) o[(size_t)row * NR + k] = x[k];
+    if (mode == 2)
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
+        rz[k] = fma(rpre[k], x[k], rz[k]);
+        qz[k] = fma(qpre[k], x[k], qz[k]);
+      }
+  };
+  bwd_sweep<FT, C, NR>(N, NP, lr, out + base * NR, pre, post);
 
   if (mode != 2) return;
-  double v[2 * NR];
 #pragma unroll
   for (int k = 0; k < NR; ++k) {
-    v[k] = wave_sum(rz[k]);
-    v[NR + k] = wave_sum(qz[k]);
-  }
-  __shared__ int last;
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < 2 * NR; ++k) partial[(size_t)(blk_off + blockIdx.x) * 2 * NR + k] = v[k];
-    __threadfence();
-    const unsigned prev = atomicAdd(counter, 1u);
-    last = (prev == nblk_total - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  double tot[2 * NR];
-#pragma unroll
-  for (int k = 0; k < 2 * NR; ++k) tot[k] = 0.0;
-  for (unsigned b = lane; b < nblk_total; b += 64)
-#pragma unroll
-    for (int k = 0; k < 2 * NR; ++k) tot[k] += partial[(size_t)b * 2 * NR + k];
-#pragma unroll
-  for (int k = 0; k < 2 * NR; ++k) tot[k] = wave_sum(tot[k]);
-  if (lane == 0) {
-    int alld = 1;
-    for (int k = 0; k < sh->nrhs; ++k) {
-      PcgScalars& S = sc[k];
-      if (!S.done) {
-        const double rzn = tot[k];
-        if (!(rzn > 0.0)) {
-          S.status = AM_ERR_BREAKDOWN;
-          S.done = 1;
-        } else {
-          if (init)
-            S.beta = 0.0;
-          else if (sh->flexible)
-            S.beta = -S.alpha * tot[NR + k] / S.rz;
-          else
-            S.beta = rzn / S.rz;
-          S.rz = rzn;
-        }
-      }
-      alld &= S.done;
+    const double a = wave_sum(rz[k]);
+    const double b = wave_sum(qz[k]);
+    if (lane == 0) {
+      partial[(size_t)(blk_off + blockIdx.x) * 2 * NR + k] = a;
+      partial[(size_t)(blk_off + blockIdx.x) * 2 * NR + NR + k] = b;
     }
-    sh->all_done = alld;
-    *counter = 0u;
-    __threadfence();
   }
-  (void)red;
 }
 
 // MBFs: one wave per (subdomain, slot): rhs = -B_s psi_n scattered from the
@@ -422,10 +543,11 @@ __global__ __launch_bounds__(64) void k_mbf(
   __syncthreads();
   fwd_sweep<FT, C, 1>(N, NP, Lc + fac_off[s], invd + ro, col, col);
   __syncthreads();
-  auto epi = [&](int row, double (&x)[1]) {
+  auto pre = [&](int) {};
+  auto post = [&](int row, double (&x)[1]) {
     if (row < N) col[row] = x[0];
   };
-  bwd_sweep<FT, C, 1>(N, NP, Lr + fac_off[s], invd + ro, col, epi);
+  bwd_sweep<FT, C, 1>(N, NP, Lr + fac_off[s], col, pre, post);
 }
 
 template <int NR>
@@ -433,9 +555,10 @@ __global__ __launch_bounds__(256) void k_bpart(const int64_t* __restrict__ sub_p
                                                const int64_t* __restrict__ isub_ptr,
                                                const int64_t* __restrict__ mbf_off,
                                                const double* __restrict__ mbf,
+                                               const int64_t* __restrict__ bdst,
                                                const double* __restrict__ r, double* bpart) {
-  __shared__ double lds[4 * NR];
-  bpart_sub<NR>(blockIdx.x, sub_ptr, isub_ptr, mbf_off, mbf, r, bpart, lds);
+  __shared__ double lds[4 * 16];  // block sums of up to 16 values
+  bpart_sub<NR>(blockIdx.x, sub_ptr, isub_ptr, mbf_off, mbf, bdst, r, bpart, lds);
 }
 
 
@@ -500,21 +623,21 @@ template <typename FT, int NR>
 static hipError_t local_t(DeviceState& d, const double* r, double* z, const double* eta,
                           int mode, int init, hipStream_t st) {
   using IT = typename AccT<FT>::T;
-  const unsigned total = (unsigned)(d.bucket_sub[0].size() + d.bucket_sub[1].size());
   unsigned off = 0;
   for (int bk = 0; bk < 2; ++bk) {
     const int nb = (int)d.bucket_sub[bk].size();
     if (!nb) continue;
-    auto args = [&](auto kern) {
-      hipLaunchKernelGGL(kern, dim3(nb), dim3(64), 0, st, d.d_bucket_sub[bk], d.sub_ptr, d.roff,
+    auto go = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(nb), dim3(128), 0, st, d.d_bucket_sub[bk], d.sub_ptr, d.roff,
                          d.fac_off, (const FT*)d.Lc, (const FT*)d.Lr, (const IT*)d.invd, r, z,
-                         mode, d.isub_ptr, d.isub_list, d.mbf_off, d.mbf, eta, d.q,
-                         d.red.partial, d.red.counter + 2, off, total, d.sc, d.shared, init);
+                         mode, d.isub_ptr, d.isub_list, d.mbf_off, d.mbf, eta, d.q, d.red.pd,
+                         off, d.fuse_eta, d.Sinv, (int)d.NL, d.ldS, d.bpart, d.red.pb, d.m,
+                         init, d.sc, d.shared);
     };
     if (bk == 0)
-      args(k_local<FT, 1, NR>);
+      go(k_local<FT, 1, NR>);
     else
-      args(k_local<FT, 2, NR>);
+      go(k_local<FT, 2, NR>);
     off += nb;
   }
   return hipGetLastError();
@@ -535,7 +658,7 @@ static hipError_t local_nr(DeviceState& d, const double* r, double* z, const dou
 
 hipError_t launch_local_sweep(DeviceState& d, const double* r, double* z, const double* eta,
                               int nrhs, int mode, hipStream_t st) {
-  // mode >= 10 encodes the PCG init pass (mode 2 with init = 1)
+  // mode >= 10: the PCG start pass (mode 2, init = 1)
   const int init = mode >= 10 ? 1 : 0;
   const int m = mode % 10;
   switch (d.prec) {
@@ -548,11 +671,11 @@ hipError_t launch_local_sweep(DeviceState& d, const double* r, double* z, const 
 hipError_t launch_bpart(DeviceState& d, const double* r, int nrhs, hipStream_t st) {
   const dim3 g(d.m), b(256);
   switch (nrhs) {
-    case 1: hipLaunchKernelGGL(k_bpart<1>, g, b, 0, st, d.sub_ptr, d.isub_ptr, d.mbf_off, d.mbf, r, d.bpart); break;
-    case 2: hipLaunchKernelGGL(k_bpart<2>, g, b, 0, st, d.sub_ptr, d.isub_ptr, d.mbf_off, d.mbf, r, d.bpart); break;
-    case 4: hipLaunchKernelGGL(k_bpart<4>, g, b, 0, st, d.sub_ptr, d.isub_ptr, d.mbf_off, d.mbf, r, d.bpart); break;
-    case 8: hipLaunchKernelGGL(k_bpart<8>, g, b, 0, st, d.sub_ptr, d.isub_ptr, d.mbf_off, d.mbf, r, d.bpart); break;
-    case 16: hipLaunchKernelGGL(k_bpart<16>, g, b, 0, st, d.sub_ptr, d.isub_ptr, d.mbf_off, d.mbf, r, d.bpart); break;
+    case 1: hipLaunchKernelGGL(k_bpart<1>, g, b, 0, st, d.sub_ptr, d.isub_ptr, d.mbf_off, d.mbf, d.bdst, r, d.bpart); break;
+    case 2: hipLaunchKernelGGL(k_bpart<2>, g, b, 0, st, d.sub_ptr, d.isub_ptr, d.mbf_off, d.mbf, d.bdst, r, d.bpart); break;
+    case 4: hipLaunchKernelGGL(k_bpart<4>, g, b, 0, st, d.sub_ptr, d.isub_ptr, d.mbf_off, d.mbf, d.bdst, r, d.bpart); break;
+    case 8: hipLaunchKernelGGL(k_bpart<8>, g, b, 0, st, d.sub_ptr, d.isub_ptr, d.mbf_off, d.mbf, d.bdst, r, d.bpart); break;
+    case 16: hipLaunchKernelGGL(k_bpart<16>, g, b, 0, st, d.sub_ptr, d.isub_ptr, d.mbf_off, d.mbf, d.bdst, r, d.bpart); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -1,14 +1,16 @@
 // PCG kernels for gfx950 (Sec. 5: AlgMortar as the CG preconditioner; Sec. 7:
 // x0 = 0, relative residual stop).  One iteration is four launches:
-//   spmv_p   : p = z + beta p (ping-pong buffers), q = A p, (p, q) -> alpha
-//   update_xr: x += alpha p, r -= alpha q, ||r||^2 -> stop test; interface
-//              partial right-hand sides 1/4 phat^T r per (subdomain, slot)
-//   gemv     : eta = S^{-1} b                         (kernels_iface.hip)
-//   local    : z = A_i^{-1} r + sum eta_m phat^(m), (r, z) -> beta (kernels_local.hip)
-// Scalars stay on the device; every reducing launch folds its per-block
-// partial sums in its last block, in block order (deterministic).  Every
-// launch returns at once when all columns have stopped, so a captured chunk
-// of iterations can run past convergence harmlessly.
+//   spmv_p   : beta from (r, z); p = z + beta p (ping-pong buffers), q = A p, (p, q)
+//   update_xr: alpha = (r, z)/(p, q); x += alpha p, r -= alpha q, ||r||^2; the
+//              interface partial right-hand sides 1/4 phat^T r per (subdomain, slot)
+//   gemv     : stop test on ||r||; eta = S^{-1} b      (kernels_iface.hip)
+//   local    : z = A_i^{-1} r + sum eta_m phat^(m), (r, z), (q, z) (kernels_local.hip)
+// Scalars stay on the device.  A launch that needs a scalar folds the per-
+// block partial sums of the launch that produced them, in block order and
+// identically in every workgroup (deterministic, no fences, no atomics);
+// workgroup 0 stores the scalars.  Every launch returns at once when all
+// columns have stopped, so a captured chunk of iterations can run past
+// convergence harmlessly.
 #include "am_common.h"
 
 namespace am {
@@ -46,6 +48,7 @@ __global__ void k_init_scalars(PcgScalars* sc, PcgShared* sh, int nr, int nrhs, 
   const int k = threadIdx.x;
   if (k < nr) {
     PcgScalars& S = sc[k];
+    S.rzv[0] = S.rzv[1] = 0.0;
     S.rz = S.pq = S.alpha = S.beta = S.rr = S.bb = S.qz = 0.0;
     S.tol2 = tol2;
     S.it = 0;
@@ -62,129 +65,246 @@ __global__ void k_init_scalars(PcgScalars* sc, PcgShared* sh, int nr, int nrhs, 
   (void)nrhs;
 }
 
-// p_new = z + beta p_old; q = A p_new (ELL, column-major, device positions);
-// the last block turns (p, q) into alpha.
-template <int NR>
+// p_new = z + beta p_old; q = A p_new (ELL, column-major, device positions).
+// beta comes from the (r, z), (q, z) partials of the previous local launch,
+// folded by every workgroup in block order; workgroup 0 stores rz and beta.
+// All loads that do not depend on beta (the ELL row, the gathered z and
+// p_old) are issued before the fold, so the launch costs two memory round
+// trips.  Grid-stride over rows with a fixed grid, one (p, q) partial per
+// workgroup.
+template <int NR, int MAXW>
 __global__ __launch_bounds__(256) void k_spmv_p(int64_t n, int w, const int32_t* __restrict__ ec,
                                                 const double* __restrict__ ev,
                                                 const double* __restrict__ z,
                                                 const double* __restrict__ pold,
                                                 double* __restrict__ pnew, double* __restrict__ q,
-                                                double* partial, unsigned* counter,
-                                                PcgScalars* sc, PcgShared* sh) {
+                                                const double* __restrict__ pd, int npd,
+                                                double* __restrict__ pa, PcgScalars* sc,
+                                                PcgShared* sh, int parity) {
   if (all_done(sh)) return;
-  __shared__ double lds[4 * NR];
-  double beta[NR];
-#pragma unroll
-  for (int k = 0; k < NR; ++k) beta[k] = sc[k].beta;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ double lds[8 * NR];
   double pq[NR];
 #pragma unroll
   for (int k = 0; k < NR; ++k) pq[k] = 0.0;
-  if (i < n) {
-    double acc[NR];
+  bool first = true;
+  double beta[NR];
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < n; i0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = i0 + threadIdx.x;
+    const bool ok = i < n;
+    int64_t col[MAXW];
+    double v[MAXW];
 #pragma unroll
-    for (int k = 0; k < NR; ++k) acc[k] = 0.0;
-    for (int c = 0; c < w; ++c) {
-      const int64_t col = ec[(int64_t)c * n + i];
-      const double v = ev[(int64_t)c * n + i];
-#pragma unroll
-      for (int k = 0; k < NR; ++k)
-        acc[k] = fma(v, fma(beta[k], pold[col * NR + k], z[col * NR + k]), acc[k]);
+    for (int c = 0; c < MAXW; ++c) {
+      col[c] = (ok && c < w) ? ec[(int64_t)c * n + i] : 0;
+      v[c] = (ok && c < w) ? ev[(int64_t)c * n + i] : 0.0;
     }
+    double zc[MAXW][NR], pc[MAXW][NR], zi[NR], pi[NR];
+#pragma unroll
+    for (int c = 0; c < MAXW; ++c)
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
+        zc[c][k] = (c < w) ? z[col[c] * NR + k] : 0.0;
+        pc[c][k] = (c < w) ? pold[col[c] * NR + k] : 0.0;
+      }
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
-      const double pn = fma(beta[k], pold[i * NR + k], z[i * NR + k]);
-      pnew[i * NR + k] = pn;
-      q[i * NR + k] = acc[k];
-      pq[k] = pn * acc[k];
+      zi[k] = ok ? z[i * NR + k] : 0.0;
+      pi[k] = ok ? pold[i * NR + k] : 0.0;
+    }
+    if (first) {  // fold the (r, z), (q, z) partials while the gathers are in flight
+      first = false;
+      double rzq[2 * NR];
+      reduce_partials<2 * NR>(rzq, pd, (unsigned)npd, lds);
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
+        const PcgScalars S = sc[k];
+        beta[k] = 0.0;
+        if (k >= sh->nrhs || S.done) continue;
+        const double rzn = rzq[k];
+        int done = 0;
+        if (!(rzn > 0.0)) {
+          done = 1;
+        } else if (S.it > 0) {
+          const double rzo = S.rzv[1 - parity];
+          beta[k] = sh->flexible ? -S.alpha * rzq[NR + k] / rzo : rzn / rzo;
+        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+          sc[k].rzv[parity] = rzn;
+          sc[k].rz = rzn;
+          sc[k].qz = rzq[NR + k];
+          sc[k].beta = beta[k];
+          if (done) {
+            sc[k].done = 1;
+            sc[k].status = AM_ERR_BREAKDOWN;
+          }
+        }
+      }
+    }
+    if (ok) {
+      double acc[NR];
+#pragma unroll
+      for (int k = 0; k < NR; ++k) acc[k] = 0.0;
+#pragma unroll
+      for (int c = 0; c < MAXW; ++c)
+#pragma unroll
+        for (int k = 0; k < NR; ++k) acc[k] = fma(v[c], fma(beta[k], pc[c][k], zc[c][k]), acc[k]);
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
+        const double pn = fma(beta[k], pi[k], zi[k]);
+        pnew[i * NR + k] = pn;
+        q[i * NR + k] = acc[k];
+        pq[k] = fma(pn, acc[k], pq[k]);
+      }
     }
   }
   block_sum<NR>(pq, lds);
-  if (!publish_partial<NR>(pq, partial, counter, gridDim.x)) return;
-  double tot[NR];
-  reduce_partials<NR>(tot, partial, gridDim.x, lds);
-  if (threadIdx.x == 0) {
-    for (int k = 0; k < sh->nrhs; ++k) {
-      PcgScalars& S = sc[k];
-      if (S.done) continue;
-      S.pq = tot[k];
-      if (!(tot[k] > 0.0)) {
-        S.status = AM_ERR_BREAKDOWN;
-        S.done = 1;
-        S.alpha = 0.0;
-      } else {
-        S.alpha = S.rz / tot[k];
-        S.it += 1;
-      }
-    }
-    *counter = 0u;
-    __threadfence();
-  }
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < NR; ++k) pa[(size_t)blockIdx.x * NR + k] = pq[k];
 }
 
-// x += alpha p, r -= alpha q on one subdomain per block, ||r||^2, then the
-// interface partial right-hand sides from the updated r.  The last block
-// applies the stop test ||r|| <= tol ||b|| (init: records ||b||^2).
+// x += alpha p, r -= alpha q on one subdomain per workgroup, its ||r||^2
+// partial, and the interface partial right-hand sides
+//   bpart[2n + side] = 1/4 phat^(n)_s . r_s
+// from the updated r held in registers.  alpha = (r, z) / (p, Ap) from the
+// SpMV partials, folded in every workgroup; workgroup 0 stores alpha and
+// counts the iteration.  The row vectors and the MBF values are loaded before
+// the fold (one memory round trip).  Rows per thread: up to RPT.
 template <int NR>
 __global__ __launch_bounds__(256) void k_update_xr(
     const int64_t* __restrict__ sub_ptr, const int64_t* __restrict__ isub_ptr,
     const int64_t* __restrict__ mbf_off, const double* __restrict__ mbf,
-    const double* __restrict__ p, const double* __restrict__ q, double* __restrict__ x, double* r,
-    double* bpart, double* partial, unsigned* counter, PcgScalars* sc, PcgShared* sh, int init) {
+    const int64_t* __restrict__ bdst, const double* __restrict__ p, const double* __restrict__ q,
+    double* __restrict__ x, double* r, double* bpart, const double* __restrict__ pa, int npa,
+    double* __restrict__ pb, PcgScalars* sc, PcgShared* sh, int init, int parity) {
   if (all_done(sh)) return;
-  __shared__ double lds[4 * NR];
+  constexpr int RPT = 4;
+  constexpr int QB = NR <= 2 ? 8 : (NR <= 4 ? 4 : (NR <= 8 ? 2 : 1));
+  __shared__ double lds[4 * 16];
   const int s = blockIdx.x;
-  double alpha[NR];
-#pragma unroll
-  for (int k = 0; k < NR; ++k) alpha[k] = (init || sc[k].done) ? 0.0 : sc[k].alpha;
-  const int64_t b0 = sub_ptr[s], b1 = sub_ptr[s + 1];
+  const int64_t base = sub_ptr[s];
+  const int N = (int)(sub_ptr[s + 1] - base);
+  const int64_t i0 = isub_ptr[s];
+  const int ns = (int)(isub_ptr[s + 1] - i0);
+  const double* P = mbf + mbf_off[s];
+  const int tid = threadIdx.x;
+  // rows tid + 256 u, u < RPT (subdomains up to 1024 cells; larger ones loop)
   double rr[NR];
 #pragma unroll
   for (int k = 0; k < NR; ++k) rr[k] = 0.0;
-  for (int64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
+  double alpha[NR];
 #pragma unroll
-    for (int k = 0; k < NR; ++k) {
-      const int64_t o = i * NR + k;
-      if (!init) {
-        x[o] = fma(alpha[k], p[o], x[o]);
-        r[o] = fma(-alpha[k], q[o], r[o]);
+  for (int k = 0; k < NR; ++k) alpha[k] = 0.0;
+  bool have_alpha = false;
+  for (int r0 = 0; r0 < N; r0 += RPT * 256) {
+    double xv[RPT][NR], pv[RPT][NR], rv[RPT][NR], qv[RPT][NR], ph[RPT][QB];
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int row = r0 + tid + 256 * u;
+      const bool ok = row < N;
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
+        const int64_t o = (base + row) * NR + k;
+        rv[u][k] = ok ? r[o] : 0.0;
+        xv[u][k] = (ok && !init) ? x[o] : 0.0;
+        pv[u][k] = (ok && !init) ? p[o] : 0.0;
+        qv[u][k] = (ok && !init) ? q[o] : 0.0;
       }
-      rr[k] = fma(r[o], r[o], rr[k]);
+#pragma unroll
+      for (int qq = 0; qq < QB; ++qq) ph[u][qq] = (ok && qq < ns) ? P[(size_t)qq * N + row] : 0.0;
     }
-  }
-  __syncthreads();
-  bpart_sub<NR>(s, sub_ptr, isub_ptr, mbf_off, mbf, r, bpart, lds);
-  block_sum<NR>(rr, lds);
-  if (!publish_partial<NR>(rr, partial, counter, gridDim.x)) return;
-  double tot[NR];
-  reduce_partials<NR>(tot, partial, gridDim.x, lds);
-  if (threadIdx.x == 0) {
-    int alld = 1;
-    for (int k = 0; k < sh->nrhs; ++k) {
-      PcgScalars& S = sc[k];
-      if (!S.done) {
-        S.rr = tot[k];
-        if (init) {
-          S.bb = tot[k];
-          if (tot[k] == 0.0) {
-            S.conv = 1;
-            S.done = 1;
+    if (!have_alpha) {
+      have_alpha = true;
+      if (!init) {
+        double pq[NR];
+        reduce_partials<NR>(pq, pa, (unsigned)npa, lds);
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+          const PcgScalars S = sc[k];
+          if (k >= sh->nrhs || S.done) continue;
+          int done = 0;
+          if (!(pq[k] > 0.0))
+            done = 1;
+          else
+            alpha[k] = S.rzv[parity] / pq[k];
+          if (blockIdx.x == 0 && tid == 0) {
+            sc[k].pq = pq[k];
+            sc[k].alpha = alpha[k];
+            if (done) {
+              sc[k].done = 1;
+              sc[k].status = AM_ERR_BREAKDOWN;
+            } else {
+              sc[k].it = S.it + 1;
+            }
           }
-        } else if (tot[k] <= S.tol2 * S.bb) {
-          S.conv = 1;
-          S.done = 1;
-        } else if (S.it >= sh->maxit) {
-          S.status = AM_ERR_NO_CONVERGENCE;
-          S.done = 1;
         }
       }
-      alld &= S.done;
     }
-    sh->all_done = alld;
-    *counter = 0u;
-    __threadfence();
+    double vb[QB * NR];
+#pragma unroll
+    for (int t = 0; t < QB * NR; ++t) vb[t] = 0.0;
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int row = r0 + tid + 256 * u;
+      if (row >= N) continue;
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
+        const int64_t o = (base + row) * NR + k;
+        double rn = rv[u][k];
+        if (!init) {
+          x[o] = fma(alpha[k], pv[u][k], xv[u][k]);
+          rn = fma(-alpha[k], qv[u][k], rn);
+          r[o] = rn;
+        }
+        rr[k] = fma(rn, rn, rr[k]);
+        rv[u][k] = rn;
+#pragma unroll
+        for (int qq = 0; qq < QB; ++qq) vb[qq * NR + k] = fma(ph[u][qq], rn, vb[qq * NR + k]);
+      }
+    }
+    if (N <= RPT * 256) {
+      // single pass: the first QB slots from registers, the rest re-read
+      block_sum<QB * NR>(vb, lds);
+      if (tid == 0)
+#pragma unroll
+        for (int qq = 0; qq < QB; ++qq)
+          if (qq < ns)
+#pragma unroll
+            for (int k = 0; k < NR; ++k) bpart[(size_t)bdst[i0 + qq] * NR + k] = 0.25 * vb[qq * NR + k];
+      for (int q0 = QB; q0 < ns; q0 += QB) {
+        double vc[QB * NR];
+#pragma unroll
+        for (int t = 0; t < QB * NR; ++t) vc[t] = 0.0;
+#pragma unroll
+        for (int u = 0; u < RPT; ++u) {
+          const int row = tid + 256 * u;
+          if (row >= N) continue;
+#pragma unroll
+          for (int qq = 0; qq < QB; ++qq) {
+            const double phv = (q0 + qq < ns) ? P[(size_t)(q0 + qq) * N + row] : 0.0;
+#pragma unroll
+            for (int k = 0; k < NR; ++k) vc[qq * NR + k] = fma(phv, rv[u][k], vc[qq * NR + k]);
+          }
+        }
+        block_sum<QB * NR>(vc, lds);
+        if (tid == 0)
+#pragma unroll
+          for (int qq = 0; qq < QB; ++qq)
+            if (q0 + qq < ns)
+#pragma unroll
+              for (int k = 0; k < NR; ++k)
+                bpart[(size_t)bdst[i0 + q0 + qq] * NR + k] = 0.25 * vc[qq * NR + k];
+      }
+    }
   }
+  if (N > RPT * 256) {
+    __syncthreads();
+    bpart_sub<NR>(s, sub_ptr, isub_ptr, mbf_off, mbf, bdst, r, bpart, lds);
+  }
+  block_sum<NR>(rr, lds);
+  if (tid == 0)
+#pragma unroll
+    for (int k = 0; k < NR; ++k) pb[(size_t)s * NR + k] = rr[k];
 }
 
 // ||b - A x||^2 per column (device positions).
@@ -271,31 +391,50 @@ hipError_t launch_pcg_init(DeviceState& d, int nr, double tol, int maxit, int fl
 static hipError_t update_xr(DeviceState& d, int nr, int parity, int init, hipStream_t s) {
   const double* pn = d.p[1 - parity];
   AM_NR_SWITCH(nr, hipLaunchKernelGGL(k_update_xr<NR>, dim3(d.m), dim3(256), 0, s, d.sub_ptr,
-                                      d.isub_ptr, d.mbf_off, d.mbf, pn, d.q, d.x, d.r, d.bpart,
-                                      d.red.partial, d.red.counter + 1, d.sc, d.shared, init));
+                                      d.isub_ptr, d.mbf_off, d.mbf, d.bdst, pn, d.q, d.x, d.r,
+                                      d.bpart, d.red.pa, d.red.spmv_blocks, d.red.pb, d.sc,
+                                      d.shared, init, parity));
   return hipGetLastError();
 }
 
 hipError_t launch_pcg_start(DeviceState& d, int nr, hipStream_t s) {
   hipError_t e = update_xr(d, nr, 0, 1, s);
   if (e != hipSuccess) return e;
-  e = launch_iface_gemv(d, -nr, s);
-  if (e != hipSuccess) return e;
+  if (!d.fuse_eta) {
+    e = launch_iface_gemv(d, nr, 1, 1, s);
+    if (e != hipSuccess) return e;
+  }
   return launch_local_sweep(d, d.r, d.z, d.eta, nr, 12, s);
 }
 
-hipError_t launch_pcg_iteration(DeviceState& d, int nr, int parity, hipStream_t s) {
+hipError_t launch_pcg_spmv(DeviceState& d, int nr, int parity, hipStream_t s) {
   const double* po = d.p[parity];
   double* pn = d.p[1 - parity];
-  AM_NR_SWITCH(nr, hipLaunchKernelGGL(k_spmv_p<NR>, dim3(nblk(d.n)), dim3(256), 0, s, d.n,
-                                      d.ell_w, d.ell_col, d.ell_val, d.z, po, pn, d.q,
-                                      d.red.partial, d.red.counter + 0, d.sc, d.shared));
-  hipError_t e = hipGetLastError();
+  if (d.ell_w <= 8) {
+    AM_NR_SWITCH(nr, hipLaunchKernelGGL((k_spmv_p<NR, 8>), dim3(d.red.spmv_blocks), dim3(256), 0, s,
+                                        d.n, d.ell_w, d.ell_col, d.ell_val, d.z, po, pn, d.q,
+                                        d.red.pd, d.m, d.red.pa, d.sc, d.shared, parity));
+  } else {
+    AM_NR_SWITCH(nr, hipLaunchKernelGGL((k_spmv_p<NR, 32>), dim3(d.red.spmv_blocks), dim3(256), 0, s,
+                                        d.n, d.ell_w, d.ell_col, d.ell_val, d.z, po, pn, d.q,
+                                        d.red.pd, d.m, d.red.pa, d.sc, d.shared, parity));
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_update(DeviceState& d, int nr, int parity, hipStream_t s) {
+  return update_xr(d, nr, parity, 0, s);
+}
+
+hipError_t launch_pcg_iteration(DeviceState& d, int nr, int parity, hipStream_t s) {
+  hipError_t e = launch_pcg_spmv(d, nr, parity, s);
   if (e != hipSuccess) return e;
   e = update_xr(d, nr, parity, 0, s);
   if (e != hipSuccess) return e;
-  e = launch_iface_gemv(d, -nr, s);
-  if (e != hipSuccess) return e;
+  if (!d.fuse_eta) {
+    e = launch_iface_gemv(d, nr, 1, 0, s);
+    if (e != hipSuccess) return e;
+  }
   return launch_local_sweep(d, d.r, d.z, d.eta, nr, 2, s);
 }
 
