@@ -42,6 +42,15 @@ __device__ __forceinline__ float ld_fac(const float* p) { return *p; }
 __device__ __forceinline__ float ld_fac(const bf16_t* p) {
   return __builtin_bit_cast(float, ((uint32_t)*p) << 16);
 }
+// raw element loads kept in a prefetch ring, widened only when consumed
+__device__ __forceinline__ double ld_raw(const double* p) { return *p; }
+__device__ __forceinline__ float ld_raw(const float* p) { return *p; }
+__device__ __forceinline__ uint32_t ld_raw(const bf16_t* p) { return (uint32_t)*p; }
+__device__ __forceinline__ double widen(double v) { return v; }
+__device__ __forceinline__ float widen(float v) { return v; }
+__device__ __forceinline__ float widen(uint32_t v) { return __builtin_bit_cast(float, v << 16); }
+template <typename FT> struct RawT { using T = FT; };
+template <> struct RawT<bf16_t> { using T = uint32_t; };
 // round-to-nearest-even conversions from fp64
 __device__ __forceinline__ void st_fac(double* p, double v) { *p = v; }
 __device__ __forceinline__ void st_fac(float* p, double v) { *p = (float)v; }

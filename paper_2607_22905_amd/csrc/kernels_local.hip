@@ -160,12 +160,12 @@ __device__ __forceinline__ void fwd_sweep(const int N, const int NP, const FT* _
 #pragma unroll
     for (int k = 0; k < NR; ++k) acc[c][k] = row < N ? (AT)rin[(size_t)row * NR + k] : (AT)0;
   }
-  AT buf[RING][C];
+  typename RawT<FT>::T buf[RING][C];
 #pragma unroll
   for (int t = 0; t < RING; ++t) {
     const FT* colp = lc + (size_t)min(t, NP - 1) * WP;
 #pragma unroll
-    for (int c = 0; c < C; ++c) buf[t][c] = ld_fac(colp + 64 * c + lane);
+    for (int c = 0; c < C; ++c) buf[t][c] = ld_raw(colp + 64 * c + lane);
   }
   AT rn[NR];
   {
@@ -195,10 +195,10 @@ __device__ __forceinline__ void fwd_sweep(const int N, const int NP, const FT* _
         const int j = j0 + t;
         AT l[C];
 #pragma unroll
-        for (int c = 0; c < C; ++c) l[c] = buf[tt][c];
+        for (int c = 0; c < C; ++c) l[c] = widen(buf[tt][c]);
         const FT* colp = lc + (size_t)min(j + RING, NP - 1) * WP;
 #pragma unroll
-        for (int c = 0; c < C; ++c) buf[tt][c] = ld_fac(colp + 64 * c + lane);
+        for (int c = 0; c < C; ++c) buf[tt][c] = ld_raw(colp + 64 * c + lane);
         AT y[NR];
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
@@ -252,12 +252,12 @@ __device__ __forceinline__ void bwd_sweep(const int N, const int NP, const FT* _
       acc[c][k] = (row >= 0 && row < N) ? (AT)yx[(size_t)row * NR + k] : (AT)0;
   }
   // ring slot u holds the row consumed u steps (mod RING) after the start
-  AT buf[RING][C];
+  typename RawT<FT>::T buf[RING][C];
 #pragma unroll
   for (int u = 0; u < RING; ++u) {
     const FT* rowp = lr + (size_t)max(NP - 1 - u, 0) * WP;
 #pragma unroll
-    for (int c = 0; c < C; ++c) buf[u][c] = ld_fac(rowp + 64 * c + lane);
+    for (int c = 0; c < C; ++c) buf[u][c] = ld_raw(rowp + 64 * c + lane);
   }
   const int nb = NP / 64;
   AT rn[NR];
@@ -289,10 +289,10 @@ __device__ __forceinline__ void bwd_sweep(const int N, const int NP, const FT* _
         const int su = RING - 1 - tt;
         AT l[C];
 #pragma unroll
-        for (int c = 0; c < C; ++c) l[c] = buf[su][c];
+        for (int c = 0; c < C; ++c) l[c] = widen(buf[su][c]);
         const FT* rowp = lr + (size_t)max(j - RING, 0) * WP;
 #pragma unroll
-        for (int c = 0; c < C; ++c) buf[su][c] = ld_fac(rowp + 64 * c + lane);
+        for (int c = 0; c < C; ++c) buf[su][c] = ld_raw(rowp + 64 * c + lane);
         AT x[NR];
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
