@@ -209,6 +209,19 @@ am_status algmortar_export_mbf(am_handle h, int64_t iface, int32_t sub, double* 
 am_status algmortar_time_kernel(am_handle h, int32_t kernel, int32_t nrhs, int32_t reps,
                                 double* avg_ms, double* bytes);
 
+/* Measurement: algmortar_pcg with plain launches (no hipGraph), every launch
+ * bracketed by HIP events on the handle's internal stream and the stop flag
+ * read after each iteration, so the durations are those of the kernels inside
+ * a real solve (same order, same data, same cache state).  Same arguments and
+ * results as algmortar_pcg, plus kernel_ms[5] (host, out): summed launch
+ * durations in ms, and launches[5] (host, out): launch counts, indexed by the
+ * kernel numbers of algmortar_time_kernel (2 stays zero: the PCG path computes
+ * the interface partials inside kernel 4).  Launches of iterations that began
+ * after convergence are not counted. */
+am_status algmortar_pcg_profile(am_handle h, const double* b, double* x, int32_t nrhs, int64_t ld,
+                                double tol, int32_t maxit, am_info* info, double* kernel_ms,
+                                int64_t* launches, void* stream);
+
 am_status algmortar_destroy(am_handle h);
 
 /* Text of the last error on handle h, or of the calling thread's last error

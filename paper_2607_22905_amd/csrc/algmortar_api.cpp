@@ -27,6 +27,7 @@ struct am_handle_s {
   hipStream_t own = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipEvent_t evf[2] = {nullptr, nullptr};  // stop-flag copies of consecutive chunks
+  hipEvent_t evp[8] = {};                   // per-launch timing of a profiled solve
   double* tres = nullptr;  // [kMaxNRHS] ||b - Ax||^2
   double* bp = nullptr;    // permuted right-hand side
 };
@@ -190,6 +191,8 @@ am_status algmortar_destroy(am_handle h) {
   if (h->d.h_flags) hipHostFree(h->d.h_flags);
   if (h->ev0) hipEventDestroy(h->ev0);
   if (h->ev1) hipEventDestroy(h->ev1);
+  for (hipEvent_t e : h->evp)
+    if (e) hipEventDestroy(e);
   for (hipEvent_t e : h->evf)
     if (e) hipEventDestroy(e);
   if (h->own) hipStreamDestroy(h->own);
@@ -534,8 +537,84 @@ static hipError_t run_chunk(DeviceState& d, int nr, hipStream_t st) {
   return hipSuccess;
 }
 
+// Per-kernel event timing of a profiled solve: launch kinds as in
+// algmortar_time_kernel (0 local, 1 gemv, 3 spmv, 4 update).
+struct KernelProfile {
+  double ms[5] = {0, 0, 0, 0, 0};
+  int64_t launches[5] = {0, 0, 0, 0, 0};
+};
+
+// One PCG iteration with every launch bracketed by events; the stop flag is
+// read after each iteration so that no launch after convergence is timed.
+static hipError_t profiled_iteration(am_handle h, int nr, int parity, KernelProfile& kp, bool& done) {
+  DeviceState& d = h->d;
+  hipStream_t st = h->own;
+  for (int i = 0; i < 8; ++i)
+    if (!h->evp[i]) {
+      hipError_t e = hipEventCreate(&h->evp[i]);
+      if (e != hipSuccess) return e;
+    }
+  int kinds[4];
+  int nk = 0;
+  hipError_t e;
+  auto timed = [&](int kind, auto&& fn) -> hipError_t {
+    hipError_t r = hipEventRecord(h->evp[2 * nk], st);
+    if (r != hipSuccess) return r;
+    r = fn();
+    if (r != hipSuccess) return r;
+    r = hipEventRecord(h->evp[2 * nk + 1], st);
+    kinds[nk++] = kind;
+    return r;
+  };
+  if ((e = timed(3, [&] { return launch_pcg_spmv(d, nr, parity, st); })) != hipSuccess) return e;
+  if ((e = timed(4, [&] { return launch_pcg_update(d, nr, parity, st); })) != hipSuccess) return e;
+  if (!d.fuse_eta && (e = timed(1, [&] { return launch_iface_gemv(d, nr, 1, 0, st); })) != hipSuccess)
+    return e;
+  if ((e = timed(0, [&] { return launch_local_sweep(d, d.r, d.z, d.eta, nr, 2, st); })) != hipSuccess)
+    return e;
+  int32_t flag = 0;
+  if ((e = hipMemcpyAsync(&flag, &d.shared->all_done, sizeof(int32_t), hipMemcpyDeviceToHost, st)) != hipSuccess)
+    return e;
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+  // the iteration whose local launch took the stop decision ran that launch
+  // as an early exit: none of its launches are counted
+  if (!flag) {
+    for (int i = 0; i < nk; ++i) {
+      float ms = 0.f;
+      if ((e = hipEventElapsedTime(&ms, h->evp[2 * i], h->evp[2 * i + 1])) != hipSuccess) return e;
+      kp.ms[kinds[i]] += ms;
+      kp.launches[kinds[i]] += 1;
+    }
+  }
+  done = flag != 0;
+  return hipSuccess;
+}
+
+static am_status pcg_impl(am_handle h, const double* b, double* x, int32_t nrhs, int64_t ld,
+                          double tol, int32_t maxit, am_info* info, void* stream,
+                          KernelProfile* prof);
+
 am_status algmortar_pcg(am_handle h, const double* b, double* x, int32_t nrhs, int64_t ld,
                         double tol, int32_t maxit, am_info* info, void* stream) {
+  return pcg_impl(h, b, x, nrhs, ld, tol, maxit, info, stream, nullptr);
+}
+
+am_status algmortar_pcg_profile(am_handle h, const double* b, double* x, int32_t nrhs, int64_t ld,
+                                double tol, int32_t maxit, am_info* info, double* kernel_ms,
+                                int64_t* launches, void* stream) {
+  if (!kernel_ms || !launches) return fail(h, AM_ERR_ARG, "null profile output");
+  KernelProfile kp;
+  am_status s = pcg_impl(h, b, x, nrhs, ld, tol, maxit, info, stream, &kp);
+  for (int k = 0; k < 5; ++k) {
+    kernel_ms[k] = kp.ms[k];
+    launches[k] = kp.launches[k];
+  }
+  return s;
+}
+
+static am_status pcg_impl(am_handle h, const double* b, double* x, int32_t nrhs, int64_t ld,
+                          double tol, int32_t maxit, am_info* info, void* stream,
+                          KernelProfile* prof) {
   am_status s = check_vec_args(h, b, x, nrhs, ld);
   if (s != AM_OK) return s;
   if (!(tol > 0.0) || !(tol < 1.0)) return fail(h, AM_ERR_ARG, "tol must be in (0, 1)");
@@ -558,7 +637,7 @@ am_status algmortar_pcg(am_handle h, const double* b, double* x, int32_t nrhs, i
   HCHK(launch_fill(d.eta, (int64_t)std::max<int32_t>(d.ldS, 1) * nr, 0.0, st));
   HCHK(launch_pcg_init(d, nr, tol, maxit, d.prec != AM_FP64 ? 1 : 0, st));
   HCHK(launch_pcg_start(d, nr, st));
-  const bool use_graph = !(h->opt.flags & AM_FLAG_NO_GRAPH);
+  const bool use_graph = !(h->opt.flags & AM_FLAG_NO_GRAPH) && !prof;
   if (use_graph && (d.graph == nullptr || d.graph_nrhs != nr)) {
     if (d.graph) {
       HCHK(hipGraphExecDestroy(d.graph));
@@ -582,7 +661,12 @@ am_status algmortar_pcg(am_handle h, const double* b, double* x, int32_t nrhs, i
   // memory behind it and read while chunk c+1 already runs (a chunk launched
   // after convergence only runs early-exit launches).
   const int max_chunks = maxit / kChunk + 2;
-  for (int c = 0; c < max_chunks; ++c) {
+  if (prof) {
+    bool done = false;
+    for (int it = 0; it < max_chunks * kChunk && !done; ++it)
+      HCHK(profiled_iteration(h, nr, it & 1, *prof, done));
+  }
+  for (int c = 0; c < max_chunks && !prof; ++c) {
     if (use_graph)
       HCHK(hipGraphLaunch(d.graph, st));
     else
@@ -694,6 +778,9 @@ am_status algmortar_time_kernel(am_handle h, int32_t kernel, int32_t nrhs, int32
       by += 2.0 * NP * lp.wp[s2] * esz + 2.0 * NP * isz + 2.0 * N * 8.0 * nr + ns * N * 8.0;
     }
     by += (double)d.NL * 8.0 * nr;
+    // with the interface solve fused in, its operator S^{-1} (once) and the
+    // interface partial right-hand sides
+    if (d.fuse_eta) by += (double)d.NL * d.NL * 8.0 + 2.0 * d.NL * 8.0 * nr;
   } else if (kernel == 1) {
     by = (double)d.NL * d.NL * 8.0 + 3.0 * d.NL * 8.0 * nr;
   } else if (kernel == 3) {

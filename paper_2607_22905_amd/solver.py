@@ -173,6 +173,22 @@ class AlgMortar:
             check(status, self._h)
         return x, [infos[i].as_dict() for i in range(k)], status
 
+    def pcg_profile(self, b, tol, maxit=10000, out=None):
+        """PCG with plain launches, each timed with HIP events.  Returns
+        (x, info dicts, {kernel: (summed ms, launches)})."""
+        import torch
+        k = _vec(b, self.n)
+        x = torch.empty_like(b) if out is None else out
+        infos = (AmInfo * k)()
+        ms = (ctypes.c_double * 5)()
+        cnt = (c_int64 * 5)()
+        torch.cuda.synchronize()
+        check(load().algmortar_pcg_profile(self._h, c_void_p(b.data_ptr()), c_void_p(x.data_ptr()), k,
+                                           self.n, float(tol), int(maxit), ctypes.cast(infos, c_void_p),
+                                           ms, cnt, c_void_p(0)), self._h)
+        names = {0: "local", 1: "gemv", 3: "spmv", 4: "update"}
+        return x, [infos[i].as_dict() for i in range(k)], {v: (ms[i], cnt[i]) for i, v in names.items()}
+
     def time_kernel(self, kernel, nrhs=1, reps=20):
         """(average launch ms, algorithmic bytes per launch) of an apply kernel:
         "local" (band sweeps + reconstruction), "gemv", "bpart"."""

@@ -230,3 +230,20 @@ def test_c2_full_size_apply_and_pcg():
     xs = np.array(gold["x_sample"])
     assert np.abs(x[idx] - xs).max() <= 1e-6 * np.abs(xs).max()
     h.close()
+
+
+def test_pcg_profile_matches_pcg():
+    """The event-timed solve runs the same kernels in the same order: the
+    iterate is bitwise that of the graph-launched solve, and every counted
+    launch has a positive duration."""
+    A, part, m, b, ora = setup_case("layered")
+    h = am.AlgMortar(A, part, m)
+    x1, info1, _ = h.pcg(gpu(b), 1e-10)
+    x2, info2, prof = h.pcg_profile(gpu(b), 1e-10)
+    assert np.array_equal(cpu(x1), cpu(x2))
+    assert info1[0]["iterations"] == info2[0]["iterations"]
+    its = info2[0]["iterations"]
+    for name in ("local", "spmv", "update"):
+        ms, cnt = prof[name]
+        assert its - 2 <= cnt <= its + 1 and ms > 0.0
+    h.close()
