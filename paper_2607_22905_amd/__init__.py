@@ -8,6 +8,8 @@ nothing here falls back to CPU code.
 from .solver import (AlgMortar, Tpfa, adjoint_grad, partition_blocks, partition_bisect,
                      structure, structure_sizes)
 from ._lib import AlgMortarError, load
+from .autograd import AlgMortarSolve, DarcyModel
 
 __all__ = ["AlgMortar", "Tpfa", "adjoint_grad", "partition_blocks", "partition_bisect",
-           "structure", "structure_sizes", "AlgMortarError", "load"]
+           "structure", "structure_sizes", "AlgMortarError", "load", "AlgMortarSolve",
+           "DarcyModel"]

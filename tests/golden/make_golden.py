@@ -12,6 +12,13 @@ the shared input generators).
 * ``c2_pcg.json``: the 64^3 layered workload (the benchmark's): the oracle's
   apply of a seeded N(0,1) vector and its PCG solution at the workload's
   tolerance (1e-8), as norms plus values at 256 seeded cells.
+* ``c5_adjoint.json``: the 96^3 differentiation workload: the oracle's loss
+  J = 1/2 sum_obs (p - pobs)^2 (pobs from the perturbed-field forward solve),
+  its adjoint gradient dJ/dlog K at 256 seeded cells and at the 20
+  finite-difference cells (drawn among cells with |g| >= 1e-3 max|g|), and
+  the gradient's norm and maximum.  All oracle solves at tol 1e-12.
+
+    python tests/golden/make_golden.py [structure|c2|c5]
 """
 import hashlib
 import json
@@ -84,6 +91,45 @@ def c2_record():
     print("c2", res.iterations, res.true_rel_res)
 
 
+def c5_record():
+    from oracle import adjoint
+    P = make_config("c5")
+    part, _ = partition_blocks(P.dims, P.partition[1])
+    As = P.A.to_scipy()
+    pre = AlgMortarCPU(P.A, part)
+    tol = 1e-12
+    res = pcg(lambda v: As @ v, P.b, pre.apply, tol)
+    p = res.x
+    # observed pressures: forward solve with the perturbed field (own operator)
+    from workloads.tpfa import assemble
+    Ap, fp = assemble(P.faces, np.exp(P.extra["logK_pert"]), P.n, None)
+    Aps = Ap.to_scipy()
+    pre_p = AlgMortarCPU(Ap, part)
+    pobs_full = pcg(lambda v: Aps @ v, fp, pre_p.apply, tol).x
+    obs = P.extra["obs"]
+    pobs = pobs_full[obs]
+    J = adjoint.loss(p, obs, pobs)
+    lam_res = pcg(lambda v: As @ v, adjoint.dloss_dp(p, obs, pobs), pre.apply, tol)
+    g = adjoint.gradient(P.faces, P.logK, p, lam_res.x)
+    gmax = float(np.abs(g).max())
+    cand = np.flatnonzero(np.abs(g) >= 1e-3 * gmax)
+    fd_cells = np.sort(np.random.default_rng(P.extra["fd_seed"]).choice(cand, size=P.extra["n_fd"],
+                                                                       replace=False))
+    idx = np.sort(np.random.default_rng(7).choice(P.n, size=256, replace=False))
+    rec = dict(J=J, grad_norm=float(np.linalg.norm(g)), grad_max=gmax, fd_cells=fd_cells.tolist(),
+               grad_fd_cells=g[fd_cells].tolist(), sample_idx=idx.tolist(), grad_sample=g[idx].tolist(),
+               p_sample=p[idx].tolist(), pobs_sample=pobs_full[idx].tolist(),
+               iterations=dict(p=res.iterations, pobs=None, lam=lam_res.iterations), tol=tol)
+    with open(os.path.join(HERE, "c5_adjoint.json"), "w") as f:
+        json.dump(rec, f, indent=1, sort_keys=True)
+    print("c5", J, res.iterations, lam_res.iterations, gmax)
+
+
 if __name__ == "__main__":
-    main()
-    c2_record()
+    which = sys.argv[1:] or ["structure", "c2", "c5"]
+    if "structure" in which:
+        main()
+    if "c2" in which:
+        c2_record()
+    if "c5" in which:
+        c5_record()
