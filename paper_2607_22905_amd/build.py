@@ -8,6 +8,7 @@ FP32 instructions disabled.
 import os
 import subprocess
 import sys
+import time
 from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -21,6 +22,9 @@ SOURCES = [
     "host_structure.cpp",
     "algmortar_api.cpp",
     "kernels_local.hip",
+    "kernels_local_f64.hip",
+    "kernels_local_f32.hip",
+    "kernels_local_bf16.hip",
     "kernels_iface.hip",
     "kernels_pcg.hip",
     "kernels_tpfa.hip",
@@ -41,7 +45,10 @@ def _compile(src):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     lang = ["-x", "hip"] if src.endswith(".hip") else []
     cmd = [HIPCC] + COMMON + EXTRA + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+    t0 = time.time()
     r = subprocess.run(cmd, capture_output=True, text=True)
+    if os.environ.get("ALGMORTAR_BUILD_TIMES"):
+        print(f"  {src}: {time.time() - t0:.0f} s", flush=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile of {src} failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     return obj
@@ -49,7 +56,7 @@ def _compile(src):
 
 def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
+    with ThreadPoolExecutor(max_workers=min(9, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs

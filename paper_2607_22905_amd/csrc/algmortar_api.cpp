@@ -238,6 +238,11 @@ am_status algmortar_setup(const am_csr* A, const int32_t* part, int32_t nparts,
     fail(h, AM_ERR_UNSUPPORTED, "a subdomain touches more than 128 mortar basis functions");
     return bail(AM_ERR_UNSUPPORTED);
   }
+  if (lp.max_ni > 64 && pow2_at_least(std::max(opt.max_nrhs, 1)) >= 8) {
+    fail(h, AM_ERR_UNSUPPORTED,
+         "with 8 or more right-hand sides a subdomain may touch at most 64 mortar basis functions");
+    return bail(AM_ERR_UNSUPPORTED);
+  }
 
   DeviceState& d = h->d;
   d.device = opt.device;
@@ -251,7 +256,13 @@ am_status algmortar_setup(const am_csr* A, const int32_t* part, int32_t nparts,
   // small interface inverses are applied inside the local kernel (each
   // subdomain multiplies its own rows; every row is read twice)
   d.fuse_eta = (d.NL > 0 && (double)d.NL * d.NL * 8.0 <= 64.0 * 1024 * 1024) ? 1 : 0;
+  // the tile kernel folds the per-wave partial rows in its second tile buffer
+  // (at least 8 KB for every factor precision and window)
+  if ((int64_t)lp.max_ni * pow2_at_least(std::max(opt.max_nrhs, 1)) * 8 * 8 > 8192) d.fuse_eta = 0;
   if (const char* env = getenv("ALGMORTAR_FUSE_ETA")) d.fuse_eta = atoi(env) && d.NL > 0;
+  if (const char* env = getenv("ALGMORTAR_BAND_SWEEP")) d.block_sweep = atoi(env) ? 0 : 1;
+  for (int32_t s2 = 0; s2 < st.m; ++s2)
+    d.max_np = std::max<int32_t>(d.max_np, (int32_t)(lp.roff[s2 + 1] - lp.roff[s2]));
 
   auto hipfail = [&](hipError_t he, const char* what) {
     fail(h, he == hipErrorOutOfMemory ? AM_ERR_OOM : AM_ERR_HIP,
@@ -451,6 +462,7 @@ am_status algmortar_setup(const am_csr* A, const int32_t* part, int32_t nparts,
   // ---- Algorithm 1 on the device ----
   SCHK(launch_band_factor(d, sm));
   SCHK(launch_mbf(d, sm));
+  if (d.block_sweep) SCHK(launch_invert_diag(d, sm));
   SCHK(launch_assemble_S(d, sm));
   if (NL > 0) {
     double *L = nullptr, *Li = nullptr;

@@ -49,6 +49,12 @@ __device__ __forceinline__ uint32_t ld_raw(const bf16_t* p) { return (uint32_t)*
 __device__ __forceinline__ double widen(double v) { return v; }
 __device__ __forceinline__ float widen(float v) { return v; }
 __device__ __forceinline__ float widen(uint32_t v) { return __builtin_bit_cast(float, v << 16); }
+// LDS copies of factor tiles keep the storage type; widened when read
+__device__ __forceinline__ double widen_lds(double v) { return v; }
+__device__ __forceinline__ float widen_lds(float v) { return v; }
+__device__ __forceinline__ float widen_lds(bf16_t v) {
+  return __builtin_bit_cast(float, (uint32_t)v << 16);
+}
 template <typename FT> struct RawT { using T = FT; };
 template <> struct RawT<bf16_t> { using T = uint32_t; };
 // round-to-nearest-even conversions from fp64

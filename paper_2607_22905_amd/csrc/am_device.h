@@ -63,6 +63,8 @@ struct DeviceState {
   int32_t ldS = 0;  // padded interface dimension (multiple of kTile)
   int32_t fuse_eta = 0;  // local kernel computes its own rows of eta = S^{-1} b
   int32_t max_nrhs = 1;
+  int32_t block_sweep = 1;  // solve-time sweeps on the block form (diagonal blocks inverted)
+  int32_t max_np = 0;       // largest padded subdomain row count
 
   // device ordering and permuted matrix
   int32_t* dperm = nullptr;    // [n] device position -> original index
@@ -130,6 +132,8 @@ struct DeviceState {
 // ---- launchers (kernels_local.hip) ----
 hipError_t launch_band_factor(DeviceState& d, hipStream_t s);
 hipError_t launch_mbf(DeviceState& d, hipStream_t s);
+// replaces the 64 x 64 diagonal blocks of both factor layouts by their inverses
+hipError_t launch_invert_diag(DeviceState& d, hipStream_t s);
 // z = A_i^{-1} r (+ prolongation with eta when eta != nullptr); dots when dot_out
 hipError_t launch_local_sweep(DeviceState& d, const double* r, double* z, const double* eta,
                               int nrhs, int mode, hipStream_t s);

@@ -247,3 +247,34 @@ def test_pcg_profile_matches_pcg():
         ms, cnt = prof[name]
         assert its - 2 <= cnt <= its + 1 and ms > 0.0
     h.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_pcg_16_rhs_bisect(prec):
+    """Batching form: 16 right-hand sides solved together on the bisection
+    partition (uneven subdomains, window widths 64 and 128); every column
+    matches its own single-RHS oracle solve and the library's own
+    single-RHS solve (columns do not interact)."""
+    A, part, m, b, ora = setup_case("bisect")
+    rng = np.random.default_rng(16)
+    n = A.n
+    B = np.zeros((16, n))
+    wells = rng.choice(n, size=32, replace=False)
+    for c in range(16):
+        B[c, wells[2 * c]] += 1.0
+        B[c, wells[2 * c + 1]] -= 1.0
+    B[0] = b
+    h = am.AlgMortar(A, part, m, prec=prec, max_nrhs=16)
+    X, infos, _ = h.pcg(gpu(B), 1e-10)
+    X = cpu(X)
+    As = A.to_scipy()
+    for c in (0, 5, 15):
+        ref = pcg(lambda v: As @ v, B[c], ora.apply, 1e-10)
+        assert rel(X[c], ref.x) <= 1e-8
+        if prec == "fp64":
+            assert abs(infos[c]["iterations"] - ref.iterations) <= 1
+        assert infos[c]["converged"] == 1 and infos[c]["true_rel_res"] <= 1e-9
+    x5, info5, _ = h.pcg(gpu(B[5]), 1e-10)
+    assert abs(info5[0]["iterations"] - infos[5]["iterations"]) <= 1
+    assert rel(cpu(x5), X[5]) <= 1e-8
+    h.close()
