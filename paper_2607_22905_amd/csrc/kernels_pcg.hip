@@ -68,10 +68,11 @@ __global__ void k_init_scalars(PcgScalars* sc, PcgShared* sh, int nr, int nrhs, 
 // p_new = z + beta p_old; q = A p_new (ELL, column-major, device positions).
 // beta comes from the (r, z), (q, z) partials of the previous local launch,
 // folded by every workgroup in block order; workgroup 0 stores rz and beta.
-// All loads that do not depend on beta (the ELL row, the gathered z and
-// p_old) are issued before the fold, so the launch costs two memory round
-// trips.  Grid-stride over rows with a fixed grid, one (p, q) partial per
-// workgroup.
+// Every load that does not depend on another one is issued first (the stop
+// flag, the scalars, the partials to fold, the ELL rows), then the gathers;
+// the stop decision and the fold are taken once they are in flight, so the
+// launch costs two memory round trips.  Grid-stride over rows with a fixed
+// grid, one (p, q) partial per workgroup.
 template <int NR, int MAXW>
 __global__ __launch_bounds__(256) void k_spmv_p(int64_t n, int w, const int32_t* __restrict__ ec,
                                                 const double* __restrict__ ev,
@@ -81,8 +82,24 @@ __global__ __launch_bounds__(256) void k_spmv_p(int64_t n, int w, const int32_t*
                                                 const double* __restrict__ pd, int npd,
                                                 double* __restrict__ pa, PcgScalars* sc,
                                                 PcgShared* sh, int parity) {
-  if (all_done(sh)) return;
   __shared__ double lds[8 * NR];
+  const int done_flag = *(volatile const int32_t*)&sh->all_done;
+  const int nrhs = sh->nrhs, flexible = sh->flexible;
+  double rzo[NR], alph[NR];
+  int sdone[NR], sit[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    rzo[k] = sc[k].rzv[1 - parity];
+    alph[k] = sc[k].alpha;
+    sdone[k] = sc[k].done;
+    sit[k] = sc[k].it;
+  }
+  double rzq[2 * NR];
+#pragma unroll
+  for (int k = 0; k < 2 * NR; ++k) rzq[k] = 0.0;
+  for (int bb = threadIdx.x; bb < npd; bb += blockDim.x)
+#pragma unroll
+    for (int k = 0; k < 2 * NR; ++k) rzq[k] += pd[(size_t)bb * 2 * NR + k];
   double pq[NR];
 #pragma unroll
   for (int k = 0; k < NR; ++k) pq[k] = 0.0;
@@ -100,33 +117,31 @@ __global__ __launch_bounds__(256) void k_spmv_p(int64_t n, int w, const int32_t*
     }
     double zc[MAXW][NR], pc[MAXW][NR], zi[NR], pi[NR];
 #pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      zi[k] = ok ? z[i * NR + k] : 0.0;
+      pi[k] = ok ? pold[i * NR + k] : 0.0;
+    }
+#pragma unroll
     for (int c = 0; c < MAXW; ++c)
 #pragma unroll
       for (int k = 0; k < NR; ++k) {
         zc[c][k] = (c < w) ? z[col[c] * NR + k] : 0.0;
         pc[c][k] = (c < w) ? pold[col[c] * NR + k] : 0.0;
       }
-#pragma unroll
-    for (int k = 0; k < NR; ++k) {
-      zi[k] = ok ? z[i * NR + k] : 0.0;
-      pi[k] = ok ? pold[i * NR + k] : 0.0;
-    }
     if (first) {  // fold the (r, z), (q, z) partials while the gathers are in flight
       first = false;
-      double rzq[2 * NR];
-      reduce_partials<2 * NR>(rzq, pd, (unsigned)npd, lds);
+      block_sum<2 * NR>(rzq, lds);
+      if (done_flag) return;  // uniform: every thread read the same flag
 #pragma unroll
       for (int k = 0; k < NR; ++k) {
-        const PcgScalars S = sc[k];
         beta[k] = 0.0;
-        if (k >= sh->nrhs || S.done) continue;
+        if (k >= nrhs || sdone[k]) continue;
         const double rzn = rzq[k];
         int done = 0;
         if (!(rzn > 0.0)) {
           done = 1;
-        } else if (S.it > 0) {
-          const double rzo = S.rzv[1 - parity];
-          beta[k] = sh->flexible ? -S.alpha * rzq[NR + k] / rzo : rzn / rzo;
+        } else if (sit[k] > 0) {
+          beta[k] = flexible ? -alph[k] * rzq[NR + k] / rzo[k] : rzn / rzo[k];
         }
         if (blockIdx.x == 0 && threadIdx.x == 0) {
           sc[k].rzv[parity] = rzn;
@@ -157,6 +172,10 @@ __global__ __launch_bounds__(256) void k_spmv_p(int64_t n, int w, const int32_t*
       }
     }
   }
+  if (first) {  // a workgroup with no rows still folds (and may be workgroup 0)
+    block_sum<2 * NR>(rzq, lds);
+    if (done_flag) return;
+  }
   block_sum<NR>(pq, lds);
   if (threadIdx.x == 0)
 #pragma unroll
@@ -177,10 +196,28 @@ __global__ __launch_bounds__(256) void k_update_xr(
     const int64_t* __restrict__ bdst, const double* __restrict__ p, const double* __restrict__ q,
     double* __restrict__ x, double* r, double* bpart, const double* __restrict__ pa, int npa,
     double* __restrict__ pb, PcgScalars* sc, PcgShared* sh, int init, int parity) {
-  if (all_done(sh)) return;
   constexpr int RPT = 4;
   constexpr int QB = NR <= 2 ? 8 : (NR <= 4 ? 4 : (NR <= 8 ? 2 : 1));
   __shared__ double lds[4 * 16];
+  // stop flag, scalars and the (p, Ap) partials are loaded before the rows
+  // (all independent), the decisions taken once the rows are in flight
+  const int done_flag = *(volatile const int32_t*)&sh->all_done;
+  const int nrhs = sh->nrhs;
+  double rzc[NR];
+  int sdone[NR], sit[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    rzc[k] = sc[k].rzv[parity];
+    sdone[k] = sc[k].done;
+    sit[k] = sc[k].it;
+  }
+  double pqs[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) pqs[k] = 0.0;
+  if (!init)
+    for (int bb = threadIdx.x; bb < npa; bb += blockDim.x)
+#pragma unroll
+      for (int k = 0; k < NR; ++k) pqs[k] += pa[(size_t)bb * NR + k];
   const int s = blockIdx.x;
   const int64_t base = sub_ptr[s];
   const int N = (int)(sub_ptr[s + 1] - base);
@@ -215,26 +252,25 @@ __global__ __launch_bounds__(256) void k_update_xr(
     }
     if (!have_alpha) {
       have_alpha = true;
+      if (!init) block_sum<NR>(pqs, lds);
+      if (done_flag) return;  // uniform
       if (!init) {
-        double pq[NR];
-        reduce_partials<NR>(pq, pa, (unsigned)npa, lds);
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
-          const PcgScalars S = sc[k];
-          if (k >= sh->nrhs || S.done) continue;
+          if (k >= nrhs || sdone[k]) continue;
           int done = 0;
-          if (!(pq[k] > 0.0))
+          if (!(pqs[k] > 0.0))
             done = 1;
           else
-            alpha[k] = S.rzv[parity] / pq[k];
+            alpha[k] = rzc[k] / pqs[k];
           if (blockIdx.x == 0 && tid == 0) {
-            sc[k].pq = pq[k];
+            sc[k].pq = pqs[k];
             sc[k].alpha = alpha[k];
             if (done) {
               sc[k].done = 1;
               sc[k].status = AM_ERR_BREAKDOWN;
             } else {
-              sc[k].it = S.it + 1;
+              sc[k].it = sit[k] + 1;
             }
           }
         }

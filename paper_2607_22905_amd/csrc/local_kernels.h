@@ -403,8 +403,13 @@ constexpr int kEtaChunk = 24;  // interface columns per lane per chunk of the fu
 template <int NR>
 __device__ __forceinline__ bool stop_test(const double* __restrict__ pb, int npb, int init,
                                           PcgScalars* sc, PcgShared* sh, bool writer = true) {
-  // one wave: fold the ||r||^2 partials in block order (same order in every workgroup)
+  // one wave: fold the ||r||^2 partials in block order (same order in every
+  // workgroup); the scalars are loaded first, independently of the partials
   const int lane = threadIdx.x & 63;
+  const int nrhs = sh->nrhs, maxit = sh->maxit;
+  PcgScalars S[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) S[k] = sc[k];
   double rr[NR];
 #pragma unroll
   for (int k = 0; k < NR; ++k) rr[k] = 0.0;
@@ -414,17 +419,18 @@ __device__ __forceinline__ bool stop_test(const double* __restrict__ pb, int npb
 #pragma unroll
   for (int k = 0; k < NR; ++k) rr[k] = wave_sum(rr[k]);
   int alld = 1;
-  for (int k = 0; k < sh->nrhs; ++k) {
-    const PcgScalars S = sc[k];
-    int done = S.done, conv = S.conv, status = S.status;
-    double bb = S.bb;
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    if (k >= nrhs) continue;
+    int done = S[k].done, conv = S[k].conv, status = S[k].status;
+    double bb = S[k].bb;
     if (!done) {
       if (init) {
         bb = rr[k];
         if (bb == 0.0) done = conv = 1;
-      } else if (rr[k] <= S.tol2 * S.bb) {
+      } else if (rr[k] <= S[k].tol2 * S[k].bb) {
         done = conv = 1;
-      } else if (S.it >= sh->maxit) {
+      } else if (S[k].it >= maxit) {
         done = 1;
         status = AM_ERR_NO_CONVERGENCE;
       }
@@ -630,7 +636,6 @@ __global__ __launch_bounds__(64 * G * W) void k_localt(
   constexpr int NLD = 64 * WP / (VEC * NTHR);
   static_assert((64 * WP) % (VEC * NTHR) == 0, "tile must split into 16-byte loads");
   constexpr int CW = 64 / W;  // columns of a pass per wave
-  if (mode == 2 && all_done(sh)) return;
   __shared__ FT tile[2][C * CH];
   __shared__ AT red[2][G][W > 1 ? W : 1][C][W > 1 ? 64 * NR : 1];
   __shared__ double eta_s[TileMaxNi<NT>::v * NT];
@@ -688,6 +693,7 @@ __global__ __launch_bounds__(64 * G * W) void k_localt(
   };
 
   tile_load(0, 0);
+  if (mode == 2 && all_done(sh)) return;  // (after the first tile is in flight)
   // ---- stop test and eta (every wave takes part) ----
   // Fused interface solve: wave v forms, for every row q of this subdomain,
   // the partial dot of S^{-1}[I_s[q], m] with b_m over its share of the
