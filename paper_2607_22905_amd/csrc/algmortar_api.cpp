@@ -260,7 +260,6 @@ am_status algmortar_setup(const am_csr* A, const int32_t* part, int32_t nparts,
   // (at least 8 KB for every factor precision and window)
   if ((int64_t)lp.max_ni * pow2_at_least(std::max(opt.max_nrhs, 1)) * 8 * 8 > 8192) d.fuse_eta = 0;
   if (const char* env = getenv("ALGMORTAR_FUSE_ETA")) d.fuse_eta = atoi(env) && d.NL > 0;
-  if (const char* env = getenv("ALGMORTAR_BAND_SWEEP")) d.block_sweep = atoi(env) ? 0 : 1;
   for (int32_t s2 = 0; s2 < st.m; ++s2)
     d.max_np = std::max<int32_t>(d.max_np, (int32_t)(lp.roff[s2 + 1] - lp.roff[s2]));
 
@@ -462,7 +461,8 @@ am_status algmortar_setup(const am_csr* A, const int32_t* part, int32_t nparts,
   // ---- Algorithm 1 on the device ----
   SCHK(launch_band_factor(d, sm));
   SCHK(launch_mbf(d, sm));
-  if (d.block_sweep) SCHK(launch_invert_diag(d, sm));
+  // solve-time form of the factor: inverted diagonal blocks, column layout only
+  SCHK(launch_invert_diag(d, sm));
   SCHK(launch_assemble_S(d, sm));
   if (NL > 0) {
     double *L = nullptr, *Li = nullptr;
@@ -491,7 +491,15 @@ am_status algmortar_setup(const am_csr* A, const int32_t* part, int32_t nparts,
     fail(h, AM_ERR_NOT_SPD, "interface matrix S not SPD at row " + std::to_string(fl[2]));
     return bail(AM_ERR_NOT_SPD);
   }
-  // free set-up only arrays
+  // free set-up only arrays: the row layout of the factor served the
+  // set-up solves of the basis functions only
+  for (auto it = d.allocs.begin(); it != d.allocs.end(); ++it)
+    if (*it == d.Lr) {
+      hipFree(*it);
+      d.allocs.erase(it);
+      break;
+    }
+  d.Lr = nullptr;
   *out = h;
   return AM_OK;
 #undef SCHK

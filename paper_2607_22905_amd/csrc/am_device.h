@@ -63,7 +63,6 @@ struct DeviceState {
   int32_t ldS = 0;  // padded interface dimension (multiple of kTile)
   int32_t fuse_eta = 0;  // local kernel computes its own rows of eta = S^{-1} b
   int32_t max_nrhs = 1;
-  int32_t block_sweep = 1;  // solve-time sweeps on the block form (diagonal blocks inverted)
   int32_t max_np = 0;       // largest padded subdomain row count
 
   // device ordering and permuted matrix
@@ -81,7 +80,7 @@ struct DeviceState {
   int64_t* roff = nullptr;     // [m+1] padded row offsets of the factor blocks
   int64_t* fac_off = nullptr;  // [m+1] element offsets of the factor blocks
   void* Lc = nullptr;          // band factor, column layout (precision dependent)
-  void* Lr = nullptr;          // band factor, row layout
+  void* Lr = nullptr;          // band factor, row layout (set-up only; freed after)
   void* invd = nullptr;        // [n] 1/L_jj (double for FP64, float otherwise)
   std::vector<int32_t> bucket_sub[2];  // host: subdomain ids per window width 64/128
   int32_t* d_bucket_sub[2] = {nullptr, nullptr};
@@ -132,7 +131,7 @@ struct DeviceState {
 // ---- launchers (kernels_local.hip) ----
 hipError_t launch_band_factor(DeviceState& d, hipStream_t s);
 hipError_t launch_mbf(DeviceState& d, hipStream_t s);
-// replaces the 64 x 64 diagonal blocks of both factor layouts by their inverses
+// replaces the 64 x 64 diagonal blocks of the column layout by their inverses
 hipError_t launch_invert_diag(DeviceState& d, hipStream_t s);
 // z = A_i^{-1} r (+ prolongation with eta when eta != nullptr); dots when dot_out
 hipError_t launch_local_sweep(DeviceState& d, const double* r, double* z, const double* eta,

@@ -350,12 +350,12 @@ template <int V> struct IC { static constexpr int v = V; };
 // computes column k of X = Lt_bb^{-1} by forward substitution,
 //   X[ii][k] = delta_ik - sum_{k <= jj < ii} Lt[ii][jj] X[jj][k],
 // against the strict lower part of Lt_bb held in LDS (fp64); X replaces
-// Lt_bb in Lc (column 64b+k) and in Lr (rows 64b+ii).
+// Lt_bb in the column layout Lc (column 64b+k, rows below the diagonal).
 template <typename FT, int C>
 __global__ __launch_bounds__(64) void k_invert_diag(const int32_t* __restrict__ subs,
                                                     const int64_t* __restrict__ roff,
                                                     const int64_t* __restrict__ fac_off,
-                                                    FT* __restrict__ Lc, FT* __restrict__ Lr) {
+                                                    FT* __restrict__ Lc) {
   constexpr int WP = 64 * C;
   constexpr int PL = 65;  // LDS pitch (doubles)
   __shared__ double Ld[64 * PL];
@@ -366,7 +366,6 @@ __global__ __launch_bounds__(64) void k_invert_diag(const int32_t* __restrict__ 
   const int b = blockIdx.y;
   if (64 * b >= NP) return;
   FT* lc = Lc + fac_off[s];
-  FT* lr = Lr + fac_off[s];
   const int lane = threadIdx.x;
   const int cb = b % C;
   for (int jj = 0; jj < 64; ++jj)
@@ -378,27 +377,14 @@ __global__ __launch_bounds__(64) void k_invert_diag(const int32_t* __restrict__ 
     for (int jj = lane; jj < ii; ++jj) a = fma(-Ld[ii * PL + jj], X[jj * PL + lane], a);
     X[ii * PL + lane] = a;
   }
-  for (int ii = lane + 1; ii < 64; ++ii)
-    st_fac(lc + (size_t)(64 * b + lane) * WP + 64 * cb + ii, X[ii * PL + lane]);
   __syncthreads();
-  for (int ii = 1; ii < 64; ++ii)
-    if (lane < ii) st_fac(lr + (size_t)(64 * b + ii) * WP + 64 * cb + lane, X[ii * PL + lane]);
+  // column 64b+jj of Lc: rows ii > jj of the block (coalesced over ii)
+  for (int jj = 0; jj < 64; ++jj)
+    if (lane > jj) st_fac(lc + (size_t)(64 * b + jj) * WP + 64 * cb + lane, X[lane * PL + jj]);
 }
 
 // ---------------------------------------------------------------------------
-// Local solve / apply kernel, one subdomain per workgroup of two waves.
-//   mode 0: out = A_i^{-1} r                          (local particular solution)
-//   mode 1: out = A_i^{-1} r + sum_q eta_q phat^(q)    (preconditioner apply)
-//   mode 2: mode 1 plus this block's (r, z) and (q, z) partial sums for PCG
-// Wave 0 runs the two band sweeps.  Wave 1 gathers eta for the subdomain's
-// basis functions while wave 0 runs the forward sweep: from the global eta
-// (computed by the interface GEMV) or, when fuse_eta is set, as the
-// subdomain's own rows of eta = S^{-1} b (so no separate interface launch is
-// needed); in PCG mode with fuse_eta it also folds the ||r||^2 partials and
-// applies the stop test ||r|| <= tol ||b|| (workgroup 0 stores the outcome).
-constexpr int kMaxNiLds = 128;
 constexpr int kPreQ = 8;  // MBF columns whose values are fetched a block ahead
-constexpr int kEtaChunk = 24;  // interface columns per lane per chunk of the fused rows
 
 template <int NR>
 __device__ __forceinline__ bool stop_test(const double* __restrict__ pb, int npb, int init,
@@ -446,145 +432,6 @@ __device__ __forceinline__ bool stop_test(const double* __restrict__ pb, int npb
   }
   if (blockIdx.x == 0 && lane == 0 && writer) sh->all_done = alld;
   return alld != 0;
-}
-
-template <typename FT, int C, int NR>
-__global__ __launch_bounds__(128) void k_local(
-    const int32_t* __restrict__ subs, const int64_t* __restrict__ sub_ptr,
-    const int64_t* __restrict__ roff, const int64_t* __restrict__ fac_off,
-    const FT* __restrict__ Lc, const FT* __restrict__ Lr,
-    const typename AccT<FT>::T* __restrict__ dinv, const double* rin, double* out, int mode,
-    const int64_t* __restrict__ isub_ptr, const int32_t* __restrict__ isub_list,
-    const int64_t* __restrict__ mbf_off, const double* __restrict__ mbf,
-    const double* __restrict__ eta, const double* __restrict__ qv, double* __restrict__ partial,
-    unsigned blk_off, int fuse_eta, const double* __restrict__ Sinv, int NL, int ldS,
-    const double* __restrict__ bpart, const double* __restrict__ pb, int npb, int init,
-    PcgScalars* sc, PcgShared* sh) {
-  if (mode == 2 && all_done(sh)) return;
-  __shared__ double eta_s[kMaxNiLds * NR];
-  __shared__ int stop_s;
-  const int s = subs[blockIdx.x];
-  const int64_t base = sub_ptr[s];
-  const int N = (int)(sub_ptr[s + 1] - base);
-  const int64_t ro = roff[s];
-  const int NP = (int)(roff[s + 1] - ro);
-  const FT* lc = Lc + fac_off[s];
-  const FT* lr = Lr + fac_off[s];
-  const auto* dv = dinv + ro;
-  const int wave = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  const int64_t i0 = isub_ptr[s];
-  const int ns = mode >= 1 ? (int)(isub_ptr[s + 1] - i0) : 0;
-  const double* P = mbf + mbf_off[s];
-
-  if (wave == 0) {
-    fwd_sweep<FT, C, NR>(N, NP, lc, dv, rin + base * NR, out + base * NR);
-  } else {
-    int stop = 0;
-    if (mode == 2 && fuse_eta) stop = stop_test<NR>(pb, npb, init, sc, sh) ? 1 : 0;
-    if (lane == 0) stop_s = stop;
-    if (!stop && ns > 0) {
-      if (!fuse_eta) {
-        for (int t = lane; t < ns * NR; t += 64)
-          eta_s[t] = eta[(size_t)isub_list[i0 + t / NR] * NR + (t % NR)];
-      } else {
-        // rows I_s[q] of S^{-1} times b, b_m = bpart[2m] + bpart[2m+1]
-        for (int q = 0; q < ns; ++q)
-          if (lane == 0)
-#pragma unroll
-            for (int k = 0; k < NR; ++k) eta_s[q * NR + k] = 0.0;
-        for (int m0 = 0; m0 < NL; m0 += 64 * kEtaChunk) {
-          double bv[kEtaChunk][NR];
-#pragma unroll
-          for (int u = 0; u < kEtaChunk; ++u) {
-            const int m = m0 + lane + 64 * u;
-#pragma unroll
-            for (int k = 0; k < NR; ++k)
-              bv[u][k] = m < NL ? bpart[(size_t)(2 * m) * NR + k] + bpart[(size_t)(2 * m + 1) * NR + k] : 0.0;
-          }
-          for (int q = 0; q < ns; ++q) {
-            const double* row = Sinv + (size_t)isub_list[i0 + q] * ldS;
-            double a[NR];
-#pragma unroll
-            for (int k = 0; k < NR; ++k) a[k] = 0.0;
-#pragma unroll
-            for (int u = 0; u < kEtaChunk; ++u) {
-              const int m = m0 + lane + 64 * u;
-              const double sv = m < NL ? row[m] : 0.0;
-#pragma unroll
-              for (int k = 0; k < NR; ++k) a[k] = fma(sv, bv[u][k], a[k]);
-            }
-#pragma unroll
-            for (int k = 0; k < NR; ++k) {
-              const double t = wave_sum(a[k]);
-              if (lane == 0) eta_s[q * NR + k] += t;
-            }
-          }
-        }
-      }
-    }
-  }
-  __syncthreads();
-  if (stop_s) return;
-  if (wave != 0) return;
-
-  double rz[NR], qz[NR];
-#pragma unroll
-  for (int k = 0; k < NR; ++k) rz[k] = qz[k] = 0.0;
-  double* o = out + base * NR;
-  const double* rr = rin + base * NR;
-  const double* qq = qv + base * NR;
-  double ph[kPreQ], rpre[NR], qpre[NR];
-#pragma unroll
-  for (int q = 0; q < kPreQ; ++q) ph[q] = 0.0;
-#pragma unroll
-  for (int k = 0; k < NR; ++k) rpre[k] = qpre[k] = 0.0;
-  const int npre = min(ns, kPreQ);
-  auto pre = [&](int row) {
-    if (row >= N) return;
-#pragma unroll
-    for (int q = 0; q < kPreQ; ++q)
-      if (q < npre) ph[q] = P[(size_t)q * N + row];
-    if (mode == 2)
-#pragma unroll
-      for (int k = 0; k < NR; ++k) {
-        rpre[k] = rr[(size_t)row * NR + k];
-        qpre[k] = qq[(size_t)row * NR + k];
-      }
-  };
-  auto post = [&](int row, double (&x)[NR]) {
-    if (row >= N) return;
-#pragma unroll
-    for (int q = 0; q < kPreQ; ++q)
-      if (q < npre)
-#pragma unroll
-        for (int k = 0; k < NR; ++k) x[k] = fma(ph[q], eta_s[q * NR + k], x[k]);
-    for (int q = kPreQ; q < ns; ++q) {
-      const double v = P[(size_t)q * N + row];
-#pragma unroll
-      for (int k = 0; k < NR; ++k) x[k] = fma(v, eta_s[q * NR + k], x[k]);
-    }
-#pragma unroll
-    for (int k = 0; k < NR; ++k) o[(size_t)row * NR + k] = x[k];
-    if (mode == 2)
-#pragma unroll
-      for (int k = 0; k < NR; ++k) {
-        rz[k] = fma(rpre[k], x[k], rz[k]);
-        qz[k] = fma(qpre[k], x[k], qz[k]);
-      }
-  };
-  bwd_sweep<FT, C, NR>(N, NP, lr, out + base * NR, pre, post);
-
-  if (mode != 2) return;
-#pragma unroll
-  for (int k = 0; k < NR; ++k) {
-    const double a = wave_sum(rz[k]);
-    const double b = wave_sum(qz[k]);
-    if (lane == 0) {
-      partial[(size_t)(blk_off + blockIdx.x) * 2 * NR + k] = a;
-      partial[(size_t)(blk_off + blockIdx.x) * 2 * NR + NR + k] = b;
-    }
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1164,10 +1011,10 @@ hipError_t invert_diag_t(DeviceState& d, hipStream_t st) {
     const dim3 grid(nb, (unsigned)((d.max_np + 63) / 64));
     if (bk == 0)
       hipLaunchKernelGGL((k_invert_diag<FT, 1>), grid, dim3(64), 0, st, d.d_bucket_sub[bk], d.roff,
-                         d.fac_off, (FT*)d.Lc, (FT*)d.Lr);
+                         d.fac_off, (FT*)d.Lc);
     else
       hipLaunchKernelGGL((k_invert_diag<FT, 2>), grid, dim3(64), 0, st, d.d_bucket_sub[bk], d.roff,
-                         d.fac_off, (FT*)d.Lc, (FT*)d.Lr);
+                         d.fac_off, (FT*)d.Lc);
   }
   return hipGetLastError();
 }
@@ -1204,49 +1051,15 @@ hipError_t localt_t(DeviceState& d, const double* r, double* z, const double* et
   return hipGetLastError();
 }
 
-template <typename FT, int NR>
-hipError_t local_t(DeviceState& d, const double* r, double* z, const double* eta,
-                          int mode, int init, hipStream_t st) {
-  using IT = typename AccT<FT>::T;
-  unsigned off = 0;
-  for (int bk = 0; bk < 2; ++bk) {
-    const int nb = (int)d.bucket_sub[bk].size();
-    if (!nb) continue;
-    auto go = [&](auto kern) {
-      hipLaunchKernelGGL(kern, dim3(nb), dim3(128), 0, st, d.d_bucket_sub[bk], d.sub_ptr, d.roff,
-                         d.fac_off, (const FT*)d.Lc, (const FT*)d.Lr, (const IT*)d.invd, r, z,
-                         mode, d.isub_ptr, d.isub_list, d.mbf_off, d.mbf, eta, d.q, d.red.pd,
-                         off, d.fuse_eta, d.Sinv, (int)d.NL, d.ldS, d.bpart, d.red.pb, d.m,
-                         init, d.sc, d.shared);
-    };
-    if (bk == 0)
-      go(k_local<FT, 1, NR>);
-    else
-      go(k_local<FT, 2, NR>);
-    off += nb;
-  }
-  return hipGetLastError();
-}
-
 template <typename FT>
-hipError_t local_nr(DeviceState& d, const double* r, double* z, const double* eta,
-                           int nrhs, int mode, int init, hipStream_t st) {
-  if (d.block_sweep) {
-    switch (nrhs) {
-      case 1: return localt_t<FT, 1>(d, r, z, eta, mode, init, st);
-      case 2: return localt_t<FT, 2>(d, r, z, eta, mode, init, st);
-      case 4: return localt_t<FT, 4>(d, r, z, eta, mode, init, st);
-      case 8: return localt_t<FT, 8>(d, r, z, eta, mode, init, st);
-      case 16: return localt_t<FT, 16>(d, r, z, eta, mode, init, st);
-    }
-    return hipErrorInvalidValue;
-  }
+hipError_t local_nr(DeviceState& d, const double* r, double* z, const double* eta, int nrhs,
+                    int mode, int init, hipStream_t st) {
   switch (nrhs) {
-    case 1: return local_t<FT, 1>(d, r, z, eta, mode, init, st);
-    case 2: return local_t<FT, 2>(d, r, z, eta, mode, init, st);
-    case 4: return local_t<FT, 4>(d, r, z, eta, mode, init, st);
-    case 8: return local_t<FT, 8>(d, r, z, eta, mode, init, st);
-    case 16: return local_t<FT, 16>(d, r, z, eta, mode, init, st);
+    case 1: return localt_t<FT, 1>(d, r, z, eta, mode, init, st);
+    case 2: return localt_t<FT, 2>(d, r, z, eta, mode, init, st);
+    case 4: return localt_t<FT, 4>(d, r, z, eta, mode, init, st);
+    case 8: return localt_t<FT, 8>(d, r, z, eta, mode, init, st);
+    case 16: return localt_t<FT, 16>(d, r, z, eta, mode, init, st);
   }
   return hipErrorInvalidValue;
 }
