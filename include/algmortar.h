@@ -85,6 +85,9 @@ typedef struct {
 } am_options;
 
 #define AM_FLAG_NO_GRAPH 1u /* run the PCG loop with plain launches, no hipGraph */
+/* apply eta = S^{-1} b as its own launches (row-part products, then their sum)
+ * even where S^{-1} is small enough to be applied inside the local kernel */
+#define AM_FLAG_SEPARATE_IFACE 2u
 
 typedef struct {
   int32_t iterations;  /* PCG iterations (matrix products) performed */

@@ -15,6 +15,7 @@ STATUS_NAMES = {
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 MORTAR = {"interface": 0, "edge": 1}
 AM_FLAG_NO_GRAPH = 1
+AM_FLAG_SEPARATE_IFACE = 2
 
 
 class AmCsr(ctypes.Structure):

@@ -259,7 +259,7 @@ am_status algmortar_setup(const am_csr* A, const int32_t* part, int32_t nparts,
   // the tile kernel folds the per-wave partial rows in its second tile buffer
   // (at least 8 KB for every factor precision and window)
   if ((int64_t)lp.max_ni * pow2_at_least(std::max(opt.max_nrhs, 1)) * 8 * 8 > 8192) d.fuse_eta = 0;
-  if (const char* env = getenv("ALGMORTAR_FUSE_ETA")) d.fuse_eta = atoi(env) && d.NL > 0;
+  if (opt.flags & AM_FLAG_SEPARATE_IFACE) d.fuse_eta = 0;
   for (int32_t s2 = 0; s2 < st.m; ++s2)
     d.max_np = std::max<int32_t>(d.max_np, (int32_t)(lp.roff[s2 + 1] - lp.roff[s2]));
 
@@ -432,6 +432,12 @@ am_status algmortar_setup(const am_csr* A, const int32_t* part, int32_t nparts,
   const size_t nS = (size_t)d.ldS * d.ldS;
   SCHK(dalloc(al, &d.S, nS));
   SCHK(dalloc(al, &d.Sinv, nS));
+  if (!d.fuse_eta && NL > 0) {
+    // enough (row block, part) waves to fill the chip, each part >= 64 rows
+    const int64_t nrb = (NL + 63) / 64;
+    d.op_parts = (int32_t)std::max<int64_t>(1, std::min<int64_t>({64, (4096 + nrb - 1) / nrb, NL / 64}));
+    SCHK(dalloc(al, &d.ypart, (size_t)d.op_parts * d.ldS * d.max_nrhs));
+  }
 
   const int NRm = d.max_nrhs;
   const size_t nv = (size_t)n * NRm;
@@ -802,7 +808,9 @@ am_status algmortar_time_kernel(am_handle h, int32_t kernel, int32_t nrhs, int32
     // interface partial right-hand sides
     if (d.fuse_eta) by += (double)d.NL * d.NL * 8.0 + 2.0 * d.NL * 8.0 * nr;
   } else if (kernel == 1) {
-    by = (double)d.NL * d.NL * 8.0 + 3.0 * d.NL * 8.0 * nr;
+    // S^{-1} once, the interface slots, the part sums written and read, eta
+    by = (double)d.NL * d.NL * 8.0 + 3.0 * d.NL * 8.0 * nr +
+         2.0 * d.op_parts * d.ldS * 8.0 * nr;
   } else if (kernel == 3) {
     // ELL values and columns, z and p read, p and q written
     by = (double)d.n * d.ell_w * 12.0 + 4.0 * d.n * 8.0 * nr;

@@ -123,6 +123,18 @@ __device__ __forceinline__ void reduce_partials(double (&tot)[NR], const double*
   block_sum<NR>(tot, lds);
 }
 
+// Node vectors with NT right-hand sides are stored in groups of KG columns:
+// value (row, k) at ((k / KG) * n + row) * KG + k % KG, KG = min(NT, 4).  For
+// NT <= 4 this is the row-interleaved layout row * NT + k; for more, a group
+// of four columns is contiguous over the rows (16-byte values per row), which
+// keeps the accesses of a workgroup that serves one group coalesced.
+template <int NT> struct KGroup { static constexpr int v = NT <= 4 ? NT : 4; };
+template <int NT>
+__device__ __forceinline__ size_t vix(int64_t n, int64_t row, int k) {
+  constexpr int KG = KGroup<NT>::v;
+  return ((size_t)(k / KG) * n + row) * KG + (k % KG);
+}
+
 __device__ __forceinline__ bool all_done(const PcgShared* sh) {
   return *(volatile const int32_t*)&sh->all_done != 0;
 }
@@ -136,7 +148,7 @@ __device__ __forceinline__ bool all_done(const PcgShared* sh) {
 // (A_s is symmetric and phat^(n)_s = A_s^{-1}(-B_s psi_n) = 4 A_s^{-1} w with
 // w_k = -sum a_e / 2 the weights of the edge average.)
 template <int NR>
-__device__ __forceinline__ void bpart_sub(int s, const int64_t* __restrict__ sub_ptr,
+__device__ __forceinline__ void bpart_sub(int s, int64_t n, const int64_t* __restrict__ sub_ptr,
                                           const int64_t* __restrict__ isub_ptr,
                                           const int64_t* __restrict__ mbf_off,
                                           const double* __restrict__ mbf,
@@ -156,7 +168,7 @@ __device__ __forceinline__ void bpart_sub(int s, const int64_t* __restrict__ sub
     for (int row = threadIdx.x; row < N; row += blockDim.x) {
       double rv[NR];
 #pragma unroll
-      for (int k = 0; k < NR; ++k) rv[k] = r[(size_t)(base + row) * NR + k];
+      for (int k = 0; k < NR; ++k) rv[k] = r[vix<NR>(n, base + row, k)];
 #pragma unroll
       for (int qq = 0; qq < QB; ++qq) {
         const double ph = (q0 + qq < ns) ? P[(size_t)(q0 + qq) * N + row] : 0.0;

@@ -106,6 +106,8 @@ struct DeviceState {
   int64_t* bdst = nullptr;       // [2 NL] (subdomain, slot) pair -> slot 2n + side of bpart
   double* S = nullptr;           // [ldS * ldS] symmetrised interface matrix
   double* Sinv = nullptr;        // [ldS * ldS]
+  int32_t op_parts = 1;          // row parts of the interface product (k_iface_op)
+  double* ypart = nullptr;       // [op_parts][ldS][max_nrhs] part sums of eta
 
   // work vectors in device order, row-interleaved [n][nrhs]
   double* x = nullptr;

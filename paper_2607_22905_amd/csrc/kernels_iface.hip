@@ -259,96 +259,89 @@ __global__ __launch_bounds__(256) void k_lauum(const double* Li, double* Sinv, i
 }
 
 // ---------------------------------------------------------------------------
-// eta = S^{-1} b, b_m = bpart[2m] + bpart[2m+1].  Each wave owns one row of
-// S^{-1}; b is staged through LDS in chunks of CH.  In PCG mode every
-// workgroup first folds the ||r||^2 partials of the update launch (same order
-// in every workgroup) and applies the stop test ||r|| <= tol ||b||;
-// workgroup 0 stores the outcome and a stopped solve skips the product.  The
-// first chunk of b and of the row are loaded before that fold, so a launch
-// whose interface fits one chunk costs one memory round trip.
+// eta = S^{-1} b, b_m = bpart[2m] + bpart[2m+1], as a sum of outer products
+// over the rows of the symmetric S^{-1}: eta[r] = sum_m S^{-1}[m][r] b_m.
+// Wave (rb, p) takes the 64 entries r = 64 rb + lane and the rows m of part
+// p: each row is one coalesced 64-value load and NR FMAs with b_m, a uniform
+// (scalar) load, so S^{-1} is read exactly once per product.  The part sums
+// go to ypart[p][r][k]; k_iface_reduce adds them in part order.
 template <int NR>
-__global__ __launch_bounds__(256) void k_iface_gemv(int NL, int ldS, const double* __restrict__ Sinv,
-                                                    const double* __restrict__ bpart, double* eta,
-                                                    int pcg, int init, const double* __restrict__ pb,
-                                                    int npb, PcgScalars* sc, PcgShared* sh) {
-  constexpr int CH = NR <= 2 ? 2048 : (NR <= 4 ? 1024 : 512);
-  constexpr int RV = CH / 64;            // row values per lane per chunk
-  constexpr int BV = (CH * NR) / 256;    // staged b values per thread per chunk
-  __shared__ double bs[CH * NR];
-  __shared__ double lds[4 * NR];
+__global__ __launch_bounds__(256) void k_iface_op(int NL, int ldS, const double* __restrict__ Sinv,
+                                                  const double* __restrict__ bpart,
+                                                  double* __restrict__ ypart, int P, int pcg,
+                                                  int init, const PcgShared* sh) {
   if (pcg && !init && all_done(sh)) return;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int n = blockIdx.x * 4 + w;
-  const double* row = Sinv + (size_t)min(n, max(NL - 1, 0)) * ldS;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  const int nrb = (NL + 63) / 64;
+  if (wv >= nrb * P) return;
+  const int rb = wv % nrb, p = wv / nrb;
+  const int per = (NL + P - 1) / P;
+  const int mb = p * per, me = min(NL, mb + per);
+  const int r = rb * 64 + lane;  // < ldS (padded to 64)
+  const double* col = Sinv + r;
   double acc[NR];
 #pragma unroll
   for (int k = 0; k < NR; ++k) acc[k] = 0.0;
-  for (int m0 = 0; m0 < NL || (m0 == 0 && pcg); m0 += CH) {
-    const int cnt = max(0, min(CH, NL - m0));
-    double bv[BV], sv[RV];
+#pragma unroll 8
+  for (int m = mb; m < me; ++m) {
+    const double sv = col[(size_t)m * ldS];
 #pragma unroll
-    for (int u = 0; u < BV; ++u) {
-      const int t = threadIdx.x + 256 * u;
-      const int m = m0 + t / NR, k = t % NR;
-      bv[u] = (t < cnt * NR) ? bpart[(size_t)(2 * m) * NR + k] + bpart[(size_t)(2 * m + 1) * NR + k] : 0.0;
-    }
+    for (int k = 0; k < NR; ++k)
+      acc[k] = fma(sv, bpart[(size_t)(2 * m) * NR + k] + bpart[(size_t)(2 * m + 1) * NR + k], acc[k]);
+  }
 #pragma unroll
-    for (int u = 0; u < RV; ++u) {
-      const int mm = lane + 64 * u;
-      sv[u] = (mm < cnt && n < NL) ? row[m0 + mm] : 0.0;
-    }
-    if (pcg && m0 == 0) {
-      double rr[NR];
-      reduce_partials<NR>(rr, pb, (unsigned)npb, lds);
-      int alld = 1;
-      for (int k = 0; k < sh->nrhs; ++k) {
-        const PcgScalars S = sc[k];
-        int done = S.done, conv = S.conv, status = S.status;
-        double bb = S.bb;
-        if (!done) {
-          if (init) {
-            bb = rr[k];
-            if (bb == 0.0) done = conv = 1;
-          } else if (rr[k] <= S.tol2 * S.bb) {
-            done = conv = 1;
-          } else if (S.it >= sh->maxit) {
-            done = 1;
-            status = AM_ERR_NO_CONVERGENCE;
-          }
-        }
-        alld &= done;
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-          sc[k].rr = rr[k];
-          sc[k].bb = bb;
-          sc[k].done = done;
-          sc[k].conv = conv;
-          sc[k].status = status;
+  for (int k = 0; k < NR; ++k) ypart[((size_t)p * ldS + r) * NR + k] = acc[k];
+}
+
+// eta[r][k] = sum_p ypart[p][r][k] in part order.  In PCG mode workgroup 0
+// first folds the ||r||^2 partials of the update launch and applies the stop
+// test ||r|| <= tol ||b|| (the next launches read its outcome).
+template <int NR>
+__global__ __launch_bounds__(256) void k_iface_reduce(int NL, int ldS, const double* __restrict__ ypart,
+                                                      int P, double* __restrict__ eta, int pcg,
+                                                      int init, const double* __restrict__ pb,
+                                                      int npb, PcgScalars* sc, PcgShared* sh) {
+  __shared__ double lds[4 * NR];
+  if (pcg && !init && all_done(sh)) return;
+  if (pcg && blockIdx.x == 0) {
+    const int nrhs = sh->nrhs, maxit = sh->maxit;
+    double rr[NR];
+    reduce_partials<NR>(rr, pb, (unsigned)npb, lds);
+    int alld = 1;
+    for (int k = 0; k < nrhs; ++k) {
+      const PcgScalars S = sc[k];
+      int done = S.done, conv = S.conv, status = S.status;
+      double bb = S.bb;
+      if (!done) {
+        if (init) {
+          bb = rr[k];
+          if (bb == 0.0) done = conv = 1;
+        } else if (rr[k] <= S.tol2 * S.bb) {
+          done = conv = 1;
+        } else if (S.it >= maxit) {
+          done = 1;
+          status = AM_ERR_NO_CONVERGENCE;
         }
       }
-      if (blockIdx.x == 0 && threadIdx.x == 0) sh->all_done = alld;
-      if (alld) return;
+      alld &= done;
+      if (threadIdx.x == 0) {
+        sc[k].rr = rr[k];
+        sc[k].bb = bb;
+        sc[k].done = done;
+        sc[k].conv = conv;
+        sc[k].status = status;
+      }
     }
-    if (cnt == 0) break;
-#pragma unroll
-    for (int u = 0; u < BV; ++u) {
-      const int t = threadIdx.x + 256 * u;
-      if (t < cnt * NR) bs[t] = bv[u];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < RV; ++u) {
-      const int mm = lane + 64 * u;
-      if (mm < cnt)
-#pragma unroll
-        for (int k = 0; k < NR; ++k) acc[k] = fma(sv[u], bs[mm * NR + k], acc[k]);
-    }
-    __syncthreads();
+    if (threadIdx.x == 0) sh->all_done = alld;
   }
-#pragma unroll
-  for (int k = 0; k < NR; ++k) {
-    const double v = wave_sum(acc[k]);
-    if (lane == 0 && n < NL) eta[(size_t)n * NR + k] = v;
-  }
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)NL * NR) return;
+  const int64_t r = t / NR;
+  const int k = (int)(t % NR);
+  double e = 0.0;
+  for (int p = 0; p < P; ++p) e += ypart[((size_t)p * ldS + r) * NR + k];
+  eta[r * NR + k] = e;
 }
 
 // ---------------------------------------------------------------------------
@@ -388,9 +381,13 @@ hipError_t dense_cholesky_inverse(DeviceState& d, double* L, double* Li, hipStre
 
 template <int NR>
 static void gemv_t(DeviceState& d, hipStream_t st, int pcg, int init) {
-  const unsigned nb = (unsigned)std::max<int64_t>(1, (d.NL + 3) / 4);
-  hipLaunchKernelGGL((k_iface_gemv<NR>), dim3(nb), dim3(256), 0, st, (int)d.NL, d.ldS, d.Sinv,
-                     d.bpart, d.eta, pcg, init, d.red.pb, d.m, d.sc, d.shared);
+  const int nrb = (int)((d.NL + 63) / 64);
+  const unsigned nw = (unsigned)std::max(1, nrb * d.op_parts);
+  hipLaunchKernelGGL((k_iface_op<NR>), dim3((nw + 3) / 4), dim3(256), 0, st, (int)d.NL, d.ldS,
+                     d.Sinv, d.bpart, d.ypart, d.op_parts, pcg, init, d.shared);
+  const unsigned nb = (unsigned)std::max<int64_t>(1, (d.NL * NR + 255) / 256);
+  hipLaunchKernelGGL((k_iface_reduce<NR>), dim3(nb), dim3(256), 0, st, (int)d.NL, d.ldS, d.ypart,
+                     d.op_parts, d.eta, pcg, init, d.red.pb, d.m, d.sc, d.shared);
 }
 
 hipError_t launch_iface_gemv(DeviceState& d, int nr, int pcg, int init, hipStream_t st) {

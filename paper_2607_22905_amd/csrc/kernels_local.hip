@@ -56,11 +56,11 @@ hipError_t launch_local_sweep(DeviceState& d, const double* r, double* z, const 
 hipError_t launch_bpart(DeviceState& d, const double* r, int nrhs, hipStream_t st) {
   const dim3 g(d.m), b(256);
   switch (nrhs) {
-    case 1: hipLaunchKernelGGL(k_bpart<1>, g, b, 0, st, d.sub_ptr, d.isub_ptr, d.mbf_off, d.mbf, d.bdst, r, d.bpart); break;
-    case 2: hipLaunchKernelGGL(k_bpart<2>, g, b, 0, st, d.sub_ptr, d.isub_ptr, d.mbf_off, d.mbf, d.bdst, r, d.bpart); break;
-    case 4: hipLaunchKernelGGL(k_bpart<4>, g, b, 0, st, d.sub_ptr, d.isub_ptr, d.mbf_off, d.mbf, d.bdst, r, d.bpart); break;
-    case 8: hipLaunchKernelGGL(k_bpart<8>, g, b, 0, st, d.sub_ptr, d.isub_ptr, d.mbf_off, d.mbf, d.bdst, r, d.bpart); break;
-    case 16: hipLaunchKernelGGL(k_bpart<16>, g, b, 0, st, d.sub_ptr, d.isub_ptr, d.mbf_off, d.mbf, d.bdst, r, d.bpart); break;
+    case 1: hipLaunchKernelGGL(k_bpart<1>, g, b, 0, st, d.n, d.sub_ptr, d.isub_ptr, d.mbf_off, d.mbf, d.bdst, r, d.bpart); break;
+    case 2: hipLaunchKernelGGL(k_bpart<2>, g, b, 0, st, d.n, d.sub_ptr, d.isub_ptr, d.mbf_off, d.mbf, d.bdst, r, d.bpart); break;
+    case 4: hipLaunchKernelGGL(k_bpart<4>, g, b, 0, st, d.n, d.sub_ptr, d.isub_ptr, d.mbf_off, d.mbf, d.bdst, r, d.bpart); break;
+    case 8: hipLaunchKernelGGL(k_bpart<8>, g, b, 0, st, d.n, d.sub_ptr, d.isub_ptr, d.mbf_off, d.mbf, d.bdst, r, d.bpart); break;
+    case 16: hipLaunchKernelGGL(k_bpart<16>, g, b, 0, st, d.n, d.sub_ptr, d.isub_ptr, d.mbf_off, d.mbf, d.bdst, r, d.bpart); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -23,7 +23,7 @@ __global__ __launch_bounds__(256) void k_permute_in(const int32_t* __restrict__ 
   if (i >= n) return;
   const int64_t o = dperm[i];
 #pragma unroll
-  for (int k = 0; k < NR; ++k) dst[i * NR + k] = k < nrhs ? src[k * ld + o] : 0.0;
+  for (int k = 0; k < NR; ++k) dst[vix<NR>(n, i, k)] = k < nrhs ? src[k * ld + o] : 0.0;
 }
 
 template <int NR>
@@ -35,7 +35,7 @@ __global__ __launch_bounds__(256) void k_permute_out(const int32_t* __restrict__
   const int64_t o = dperm[i];
 #pragma unroll
   for (int k = 0; k < NR; ++k)
-    if (k < nrhs) dst[k * ld + o] = src[i * NR + k];
+    if (k < nrhs) dst[k * ld + o] = src[vix<NR>(n, i, k)];
 }
 
 __global__ __launch_bounds__(256) void k_fill(double* p, int64_t cnt, double v) {
@@ -65,15 +65,19 @@ __global__ void k_init_scalars(PcgScalars* sc, PcgShared* sh, int nr, int nrhs, 
   (void)nrhs;
 }
 
+// Right-hand sides per workgroup of the PCG kernels: a workgroup takes the
+// group of KG columns given by blockIdx.x % (NT/KG) (the vector layout keeps
+// a group contiguous; see vix), so the groups of the same rows run together.
+
 // p_new = z + beta p_old; q = A p_new (ELL, column-major, device positions).
 // beta comes from the (r, z), (q, z) partials of the previous local launch,
-// folded by every workgroup in block order; workgroup 0 stores rz and beta.
-// Every load that does not depend on another one is issued first (the stop
-// flag, the scalars, the partials to fold, the ELL rows), then the gathers;
-// the stop decision and the fold are taken once they are in flight, so the
-// launch costs two memory round trips.  Grid-stride over rows with a fixed
-// grid, one (p, q) partial per workgroup.
-template <int NR, int MAXW>
+// folded by every workgroup in block order; the first workgroup of each group
+// stores rz and beta.  Every load that does not depend on another one is
+// issued first (the stop flag, the scalars, the partials to fold, the ELL
+// rows), then the gathers; the stop decision and the fold are taken once they
+// are in flight, so the launch costs two memory round trips.  Grid-stride over
+// rows with a fixed grid, one (p, q) partial per workgroup and column.
+template <int NT, int MAXW>
 __global__ __launch_bounds__(256) void k_spmv_p(int64_t n, int w, const int32_t* __restrict__ ec,
                                                 const double* __restrict__ ev,
                                                 const double* __restrict__ z,
@@ -82,30 +86,37 @@ __global__ __launch_bounds__(256) void k_spmv_p(int64_t n, int w, const int32_t*
                                                 const double* __restrict__ pd, int npd,
                                                 double* __restrict__ pa, PcgScalars* sc,
                                                 PcgShared* sh, int parity) {
-  __shared__ double lds[8 * NR];
+  constexpr int KG = KGroup<NT>::v, TR = NT / KG;
+  __shared__ double lds[8 * KG];
+  const int blk = blockIdx.x / TR, g = blockIdx.x % TR, k0 = g * KG;
+  const int nblk = gridDim.x / TR;
+  auto vi = [&](int64_t row, int k) { return ((size_t)g * n + row) * KG + k; };  // vix<NT>(n, row, k0 + k)
   const int done_flag = *(volatile const int32_t*)&sh->all_done;
   const int nrhs = sh->nrhs, flexible = sh->flexible;
-  double rzo[NR], alph[NR];
-  int sdone[NR], sit[NR];
+  double rzo[KG], alph[KG];
+  int sdone[KG], sit[KG];
 #pragma unroll
-  for (int k = 0; k < NR; ++k) {
-    rzo[k] = sc[k].rzv[1 - parity];
-    alph[k] = sc[k].alpha;
-    sdone[k] = sc[k].done;
-    sit[k] = sc[k].it;
+  for (int k = 0; k < KG; ++k) {
+    rzo[k] = sc[k0 + k].rzv[1 - parity];
+    alph[k] = sc[k0 + k].alpha;
+    sdone[k] = sc[k0 + k].done;
+    sit[k] = sc[k0 + k].it;
   }
-  double rzq[2 * NR];
+  double rzq[2 * KG];
 #pragma unroll
-  for (int k = 0; k < 2 * NR; ++k) rzq[k] = 0.0;
+  for (int k = 0; k < 2 * KG; ++k) rzq[k] = 0.0;
   for (int bb = threadIdx.x; bb < npd; bb += blockDim.x)
 #pragma unroll
-    for (int k = 0; k < 2 * NR; ++k) rzq[k] += pd[(size_t)bb * 2 * NR + k];
-  double pq[NR];
+    for (int k = 0; k < KG; ++k) {
+      rzq[k] += pd[(size_t)bb * 2 * NT + k0 + k];
+      rzq[KG + k] += pd[(size_t)bb * 2 * NT + NT + k0 + k];
+    }
+  double pq[KG];
 #pragma unroll
-  for (int k = 0; k < NR; ++k) pq[k] = 0.0;
+  for (int k = 0; k < KG; ++k) pq[k] = 0.0;
   bool first = true;
-  double beta[NR];
-  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < n; i0 += (int64_t)gridDim.x * blockDim.x) {
+  double beta[KG];
+  for (int64_t i0 = (int64_t)blk * blockDim.x; i0 < n; i0 += (int64_t)nblk * blockDim.x) {
     const int64_t i = i0 + threadIdx.x;
     const bool ok = i < n;
     int64_t col[MAXW];
@@ -115,133 +126,175 @@ __global__ __launch_bounds__(256) void k_spmv_p(int64_t n, int w, const int32_t*
       col[c] = (ok && c < w) ? ec[(int64_t)c * n + i] : 0;
       v[c] = (ok && c < w) ? ev[(int64_t)c * n + i] : 0.0;
     }
-    double zc[MAXW][NR], pc[MAXW][NR], zi[NR], pi[NR];
+    double zc[MAXW][KG], pc[MAXW][KG], zi[KG], pi[KG];
 #pragma unroll
-    for (int k = 0; k < NR; ++k) {
-      zi[k] = ok ? z[i * NR + k] : 0.0;
-      pi[k] = ok ? pold[i * NR + k] : 0.0;
+    for (int k = 0; k < KG; ++k) {
+      zi[k] = ok ? z[vi(i, k)] : 0.0;
+      pi[k] = ok ? pold[vi(i, k)] : 0.0;
     }
 #pragma unroll
     for (int c = 0; c < MAXW; ++c)
 #pragma unroll
-      for (int k = 0; k < NR; ++k) {
-        zc[c][k] = (c < w) ? z[col[c] * NR + k] : 0.0;
-        pc[c][k] = (c < w) ? pold[col[c] * NR + k] : 0.0;
+      for (int k = 0; k < KG; ++k) {
+        zc[c][k] = (c < w) ? z[vi(col[c], k)] : 0.0;
+        pc[c][k] = (c < w) ? pold[vi(col[c], k)] : 0.0;
       }
     if (first) {  // fold the (r, z), (q, z) partials while the gathers are in flight
       first = false;
-      block_sum<2 * NR>(rzq, lds);
+      block_sum<2 * KG>(rzq, lds);
       if (done_flag) return;  // uniform: every thread read the same flag
 #pragma unroll
-      for (int k = 0; k < NR; ++k) {
+      for (int k = 0; k < KG; ++k) {
         beta[k] = 0.0;
-        if (k >= nrhs || sdone[k]) continue;
+        if (k0 + k >= nrhs || sdone[k]) continue;
         const double rzn = rzq[k];
         int done = 0;
         if (!(rzn > 0.0)) {
           done = 1;
         } else if (sit[k] > 0) {
-          beta[k] = flexible ? -alph[k] * rzq[NR + k] / rzo[k] : rzn / rzo[k];
+          beta[k] = flexible ? -alph[k] * rzq[KG + k] / rzo[k] : rzn / rzo[k];
         }
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-          sc[k].rzv[parity] = rzn;
-          sc[k].rz = rzn;
-          sc[k].qz = rzq[NR + k];
-          sc[k].beta = beta[k];
+        if (blk == 0 && threadIdx.x == 0) {
+          PcgScalars& S = sc[k0 + k];
+          S.rzv[parity] = rzn;
+          S.rz = rzn;
+          S.qz = rzq[KG + k];
+          S.beta = beta[k];
           if (done) {
-            sc[k].done = 1;
-            sc[k].status = AM_ERR_BREAKDOWN;
+            S.done = 1;
+            S.status = AM_ERR_BREAKDOWN;
           }
         }
       }
     }
     if (ok) {
-      double acc[NR];
+      double acc[KG];
 #pragma unroll
-      for (int k = 0; k < NR; ++k) acc[k] = 0.0;
+      for (int k = 0; k < KG; ++k) acc[k] = 0.0;
 #pragma unroll
       for (int c = 0; c < MAXW; ++c)
 #pragma unroll
-        for (int k = 0; k < NR; ++k) acc[k] = fma(v[c], fma(beta[k], pc[c][k], zc[c][k]), acc[k]);
+        for (int k = 0; k < KG; ++k) acc[k] = fma(v[c], fma(beta[k], pc[c][k], zc[c][k]), acc[k]);
 #pragma unroll
-      for (int k = 0; k < NR; ++k) {
+      for (int k = 0; k < KG; ++k) {
         const double pn = fma(beta[k], pi[k], zi[k]);
-        pnew[i * NR + k] = pn;
-        q[i * NR + k] = acc[k];
+        pnew[vi(i, k)] = pn;
+        q[vi(i, k)] = acc[k];
         pq[k] = fma(pn, acc[k], pq[k]);
       }
     }
   }
-  if (first) {  // a workgroup with no rows still folds (and may be workgroup 0)
-    block_sum<2 * NR>(rzq, lds);
+  if (first) {  // a workgroup with no rows still folds (and may be the writer)
+    block_sum<2 * KG>(rzq, lds);
     if (done_flag) return;
   }
-  block_sum<NR>(pq, lds);
+  block_sum<KG>(pq, lds);
   if (threadIdx.x == 0)
 #pragma unroll
-    for (int k = 0; k < NR; ++k) pa[(size_t)blockIdx.x * NR + k] = pq[k];
+    for (int k = 0; k < KG; ++k) pa[(size_t)blk * NT + k0 + k] = pq[k];
 }
 
-// x += alpha p, r -= alpha q on one subdomain per workgroup, its ||r||^2
-// partial, and the interface partial right-hand sides
+// Interface partial right-hand sides of subdomain s for the KG columns
+// k0 .. k0+KG-1 of vectors with NT values per row (see bpart_sub).
+template <int NT, int KG>
+__device__ __forceinline__ void bpart_sub_g(int s, int k0, int64_t n, const int64_t* __restrict__ sub_ptr,
+                                            const int64_t* __restrict__ isub_ptr,
+                                            const int64_t* __restrict__ mbf_off,
+                                            const double* __restrict__ mbf,
+                                            const int64_t* __restrict__ bdst, const double* r,
+                                            double* bpart, double* lds) {
+  constexpr int QB = KG <= 2 ? 8 : 4;  // slots per round
+  const int64_t base = sub_ptr[s];
+  const int N = (int)(sub_ptr[s + 1] - base);
+  const int64_t i0 = isub_ptr[s];
+  const int ns = (int)(isub_ptr[s + 1] - i0);
+  const double* P = mbf + mbf_off[s];
+  for (int q0 = 0; q0 < ns; q0 += QB) {
+    double v[QB * KG];
+#pragma unroll
+    for (int t = 0; t < QB * KG; ++t) v[t] = 0.0;
+#pragma unroll 2
+    for (int row = threadIdx.x; row < N; row += blockDim.x) {
+      double rv[KG];
+#pragma unroll
+      for (int k = 0; k < KG; ++k) rv[k] = r[vix<NT>(n, base + row, k0 + k)];
+#pragma unroll
+      for (int qq = 0; qq < QB; ++qq) {
+        const double ph = (q0 + qq < ns) ? P[(size_t)(q0 + qq) * N + row] : 0.0;
+#pragma unroll
+        for (int k = 0; k < KG; ++k) v[qq * KG + k] = fma(ph, rv[k], v[qq * KG + k]);
+      }
+    }
+    block_sum<QB * KG>(v, lds);
+    if (threadIdx.x == 0)
+#pragma unroll
+      for (int qq = 0; qq < QB; ++qq)
+        if (q0 + qq < ns)
+#pragma unroll
+          for (int k = 0; k < KG; ++k)
+            bpart[(size_t)bdst[i0 + q0 + qq] * NT + k0 + k] = 0.25 * v[qq * KG + k];
+  }
+}
+
+// x += alpha p, r -= alpha q on one subdomain and column group per
+// workgroup, its ||r||^2 partial, and the interface partial right-hand sides
 //   bpart[2n + side] = 1/4 phat^(n)_s . r_s
 // from the updated r held in registers.  alpha = (r, z) / (p, Ap) from the
-// SpMV partials, folded in every workgroup; workgroup 0 stores alpha and
-// counts the iteration.  The row vectors and the MBF values are loaded before
-// the fold (one memory round trip).  Rows per thread: up to RPT.
-template <int NR>
+// SpMV partials, folded in every workgroup; the first subdomain's workgroup
+// of each group stores alpha and counts the iteration.  The stop flag,
+// scalars and partials are loaded before the rows, the decisions taken once
+// the rows are in flight.  Rows per thread: up to RPT.
+template <int NT>
 __global__ __launch_bounds__(256) void k_update_xr(
-    const int64_t* __restrict__ sub_ptr, const int64_t* __restrict__ isub_ptr,
+    int64_t n, const int64_t* __restrict__ sub_ptr, const int64_t* __restrict__ isub_ptr,
     const int64_t* __restrict__ mbf_off, const double* __restrict__ mbf,
     const int64_t* __restrict__ bdst, const double* __restrict__ p, const double* __restrict__ q,
     double* __restrict__ x, double* r, double* bpart, const double* __restrict__ pa, int npa,
     double* __restrict__ pb, PcgScalars* sc, PcgShared* sh, int init, int parity) {
+  constexpr int KG = KGroup<NT>::v, TR = NT / KG;
   constexpr int RPT = 4;
-  constexpr int QB = NR <= 2 ? 8 : (NR <= 4 ? 4 : (NR <= 8 ? 2 : 1));
-  __shared__ double lds[4 * 16];
-  // stop flag, scalars and the (p, Ap) partials are loaded before the rows
-  // (all independent), the decisions taken once the rows are in flight
+  constexpr int QB = KG <= 2 ? 8 : 4;
+  __shared__ double lds[4 * 32];
+  const int s = blockIdx.x / TR, g = blockIdx.x % TR, k0 = g * KG;
   const int done_flag = *(volatile const int32_t*)&sh->all_done;
   const int nrhs = sh->nrhs;
-  double rzc[NR];
-  int sdone[NR], sit[NR];
+  double rzc[KG];
+  int sdone[KG], sit[KG];
 #pragma unroll
-  for (int k = 0; k < NR; ++k) {
-    rzc[k] = sc[k].rzv[parity];
-    sdone[k] = sc[k].done;
-    sit[k] = sc[k].it;
+  for (int k = 0; k < KG; ++k) {
+    rzc[k] = sc[k0 + k].rzv[parity];
+    sdone[k] = sc[k0 + k].done;
+    sit[k] = sc[k0 + k].it;
   }
-  double pqs[NR];
+  double pqs[KG];
 #pragma unroll
-  for (int k = 0; k < NR; ++k) pqs[k] = 0.0;
+  for (int k = 0; k < KG; ++k) pqs[k] = 0.0;
   if (!init)
     for (int bb = threadIdx.x; bb < npa; bb += blockDim.x)
 #pragma unroll
-      for (int k = 0; k < NR; ++k) pqs[k] += pa[(size_t)bb * NR + k];
-  const int s = blockIdx.x;
+      for (int k = 0; k < KG; ++k) pqs[k] += pa[(size_t)bb * NT + k0 + k];
   const int64_t base = sub_ptr[s];
   const int N = (int)(sub_ptr[s + 1] - base);
   const int64_t i0 = isub_ptr[s];
   const int ns = (int)(isub_ptr[s + 1] - i0);
   const double* P = mbf + mbf_off[s];
   const int tid = threadIdx.x;
-  // rows tid + 256 u, u < RPT (subdomains up to 1024 cells; larger ones loop)
-  double rr[NR];
+  double rr[KG];
 #pragma unroll
-  for (int k = 0; k < NR; ++k) rr[k] = 0.0;
-  double alpha[NR];
+  for (int k = 0; k < KG; ++k) rr[k] = 0.0;
+  double alpha[KG];
 #pragma unroll
-  for (int k = 0; k < NR; ++k) alpha[k] = 0.0;
+  for (int k = 0; k < KG; ++k) alpha[k] = 0.0;
   bool have_alpha = false;
   for (int r0 = 0; r0 < N; r0 += RPT * 256) {
-    double xv[RPT][NR], pv[RPT][NR], rv[RPT][NR], qv[RPT][NR], ph[RPT][QB];
+    double xv[RPT][KG], pv[RPT][KG], rv[RPT][KG], qv[RPT][KG], ph[RPT][QB];
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {
       const int row = r0 + tid + 256 * u;
       const bool ok = row < N;
 #pragma unroll
-      for (int k = 0; k < NR; ++k) {
-        const int64_t o = (base + row) * NR + k;
+      for (int k = 0; k < KG; ++k) {
+        const size_t o = vix<NT>(n, base + row, k0 + k);
         rv[u][k] = ok ? r[o] : 0.0;
         xv[u][k] = (ok && !init) ? x[o] : 0.0;
         pv[u][k] = (ok && !init) ? p[o] : 0.0;
@@ -252,40 +305,41 @@ __global__ __launch_bounds__(256) void k_update_xr(
     }
     if (!have_alpha) {
       have_alpha = true;
-      if (!init) block_sum<NR>(pqs, lds);
+      if (!init) block_sum<KG>(pqs, lds);
       if (done_flag) return;  // uniform
       if (!init) {
 #pragma unroll
-        for (int k = 0; k < NR; ++k) {
-          if (k >= nrhs || sdone[k]) continue;
+        for (int k = 0; k < KG; ++k) {
+          if (k0 + k >= nrhs || sdone[k]) continue;
           int done = 0;
           if (!(pqs[k] > 0.0))
             done = 1;
           else
             alpha[k] = rzc[k] / pqs[k];
-          if (blockIdx.x == 0 && tid == 0) {
-            sc[k].pq = pqs[k];
-            sc[k].alpha = alpha[k];
+          if (s == 0 && tid == 0) {
+            PcgScalars& S = sc[k0 + k];
+            S.pq = pqs[k];
+            S.alpha = alpha[k];
             if (done) {
-              sc[k].done = 1;
-              sc[k].status = AM_ERR_BREAKDOWN;
+              S.done = 1;
+              S.status = AM_ERR_BREAKDOWN;
             } else {
-              sc[k].it = sit[k] + 1;
+              S.it = sit[k] + 1;
             }
           }
         }
       }
     }
-    double vb[QB * NR];
+    double vb[QB * KG];
 #pragma unroll
-    for (int t = 0; t < QB * NR; ++t) vb[t] = 0.0;
+    for (int t = 0; t < QB * KG; ++t) vb[t] = 0.0;
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {
       const int row = r0 + tid + 256 * u;
       if (row >= N) continue;
 #pragma unroll
-      for (int k = 0; k < NR; ++k) {
-        const int64_t o = (base + row) * NR + k;
+      for (int k = 0; k < KG; ++k) {
+        const size_t o = vix<NT>(n, base + row, k0 + k);
         double rn = rv[u][k];
         if (!init) {
           x[o] = fma(alpha[k], pv[u][k], xv[u][k]);
@@ -295,22 +349,22 @@ __global__ __launch_bounds__(256) void k_update_xr(
         rr[k] = fma(rn, rn, rr[k]);
         rv[u][k] = rn;
 #pragma unroll
-        for (int qq = 0; qq < QB; ++qq) vb[qq * NR + k] = fma(ph[u][qq], rn, vb[qq * NR + k]);
+        for (int qq = 0; qq < QB; ++qq) vb[qq * KG + k] = fma(ph[u][qq], rn, vb[qq * KG + k]);
       }
     }
     if (N <= RPT * 256) {
       // single pass: the first QB slots from registers, the rest re-read
-      block_sum<QB * NR>(vb, lds);
+      block_sum<QB * KG>(vb, lds);
       if (tid == 0)
 #pragma unroll
         for (int qq = 0; qq < QB; ++qq)
           if (qq < ns)
 #pragma unroll
-            for (int k = 0; k < NR; ++k) bpart[(size_t)bdst[i0 + qq] * NR + k] = 0.25 * vb[qq * NR + k];
+            for (int k = 0; k < KG; ++k) bpart[(size_t)bdst[i0 + qq] * NT + k0 + k] = 0.25 * vb[qq * KG + k];
       for (int q0 = QB; q0 < ns; q0 += QB) {
-        double vc[QB * NR];
+        double vc[QB * KG];
 #pragma unroll
-        for (int t = 0; t < QB * NR; ++t) vc[t] = 0.0;
+        for (int t = 0; t < QB * KG; ++t) vc[t] = 0.0;
 #pragma unroll
         for (int u = 0; u < RPT; ++u) {
           const int row = tid + 256 * u;
@@ -319,28 +373,28 @@ __global__ __launch_bounds__(256) void k_update_xr(
           for (int qq = 0; qq < QB; ++qq) {
             const double phv = (q0 + qq < ns) ? P[(size_t)(q0 + qq) * N + row] : 0.0;
 #pragma unroll
-            for (int k = 0; k < NR; ++k) vc[qq * NR + k] = fma(phv, rv[u][k], vc[qq * NR + k]);
+            for (int k = 0; k < KG; ++k) vc[qq * KG + k] = fma(phv, rv[u][k], vc[qq * KG + k]);
           }
         }
-        block_sum<QB * NR>(vc, lds);
+        block_sum<QB * KG>(vc, lds);
         if (tid == 0)
 #pragma unroll
           for (int qq = 0; qq < QB; ++qq)
             if (q0 + qq < ns)
 #pragma unroll
-              for (int k = 0; k < NR; ++k)
-                bpart[(size_t)bdst[i0 + q0 + qq] * NR + k] = 0.25 * vc[qq * NR + k];
+              for (int k = 0; k < KG; ++k)
+                bpart[(size_t)bdst[i0 + q0 + qq] * NT + k0 + k] = 0.25 * vc[qq * KG + k];
       }
     }
   }
   if (N > RPT * 256) {
     __syncthreads();
-    bpart_sub<NR>(s, sub_ptr, isub_ptr, mbf_off, mbf, bdst, r, bpart, lds);
+    bpart_sub_g<NT, KG>(s, k0, n, sub_ptr, isub_ptr, mbf_off, mbf, bdst, r, bpart, lds);
   }
-  block_sum<NR>(rr, lds);
+  block_sum<KG>(rr, lds);
   if (tid == 0)
 #pragma unroll
-    for (int k = 0; k < NR; ++k) pb[(size_t)s * NR + k] = rr[k];
+    for (int k = 0; k < KG; ++k) pb[(size_t)s * NT + k0 + k] = rr[k];
 }
 
 // ||b - A x||^2 per column (device positions).
@@ -358,12 +412,12 @@ __global__ __launch_bounds__(256) void k_true_res(int64_t n, int w, const int32_
   if (i < n) {
     double acc[NR];
 #pragma unroll
-    for (int k = 0; k < NR; ++k) acc[k] = b[i * NR + k];
+    for (int k = 0; k < NR; ++k) acc[k] = b[vix<NR>(n, i, k)];
     for (int c = 0; c < w; ++c) {
       const int64_t col = ec[(int64_t)c * n + i];
       const double a = ev[(int64_t)c * n + i];
 #pragma unroll
-      for (int k = 0; k < NR; ++k) acc[k] = fma(-a, x[col * NR + k], acc[k]);
+      for (int k = 0; k < NR; ++k) acc[k] = fma(-a, x[vix<NR>(n, col, k)], acc[k]);
     }
 #pragma unroll
     for (int k = 0; k < NR; ++k) v[k] = acc[k] * acc[k];
@@ -426,7 +480,7 @@ hipError_t launch_pcg_init(DeviceState& d, int nr, double tol, int maxit, int fl
 
 static hipError_t update_xr(DeviceState& d, int nr, int parity, int init, hipStream_t s) {
   const double* pn = d.p[1 - parity];
-  AM_NR_SWITCH(nr, hipLaunchKernelGGL(k_update_xr<NR>, dim3(d.m), dim3(256), 0, s, d.sub_ptr,
+  AM_NR_SWITCH(nr, hipLaunchKernelGGL(k_update_xr<NR>, dim3(d.m * (NR / KGroup<NR>::v)), dim3(256), 0, s, d.n, d.sub_ptr,
                                       d.isub_ptr, d.mbf_off, d.mbf, d.bdst, pn, d.q, d.x, d.r,
                                       d.bpart, d.red.pa, d.red.spmv_blocks, d.red.pb, d.sc,
                                       d.shared, init, parity));
@@ -447,11 +501,11 @@ hipError_t launch_pcg_spmv(DeviceState& d, int nr, int parity, hipStream_t s) {
   const double* po = d.p[parity];
   double* pn = d.p[1 - parity];
   if (d.ell_w <= 8) {
-    AM_NR_SWITCH(nr, hipLaunchKernelGGL((k_spmv_p<NR, 8>), dim3(d.red.spmv_blocks), dim3(256), 0, s,
+    AM_NR_SWITCH(nr, hipLaunchKernelGGL((k_spmv_p<NR, 8>), dim3(d.red.spmv_blocks * (NR / KGroup<NR>::v)), dim3(256), 0, s,
                                         d.n, d.ell_w, d.ell_col, d.ell_val, d.z, po, pn, d.q,
                                         d.red.pd, d.m, d.red.pa, d.sc, d.shared, parity));
   } else {
-    AM_NR_SWITCH(nr, hipLaunchKernelGGL((k_spmv_p<NR, 32>), dim3(d.red.spmv_blocks), dim3(256), 0, s,
+    AM_NR_SWITCH(nr, hipLaunchKernelGGL((k_spmv_p<NR, 32>), dim3(d.red.spmv_blocks * (NR / KGroup<NR>::v)), dim3(256), 0, s,
                                         d.n, d.ell_w, d.ell_col, d.ell_val, d.z, po, pn, d.q,
                                         d.red.pd, d.m, d.red.pa, d.sc, d.shared, parity));
   }

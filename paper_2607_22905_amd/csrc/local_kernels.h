@@ -472,7 +472,7 @@ __global__ __launch_bounds__(64 * G * W) void k_localt(
     const double* __restrict__ mbf, const double* __restrict__ eta, const double* __restrict__ qv,
     double* __restrict__ partial, unsigned blk_off, int fuse_eta, const double* __restrict__ Sinv,
     int NL, int ldS, const double* __restrict__ bpart, const double* __restrict__ pb, int npb,
-    int init, PcgScalars* sc, PcgShared* sh) {
+    int init, PcgScalars* sc, PcgShared* sh, int64_t nrows) {
   using AT = typename AccT<FT>::T;
   constexpr int NR = NT / G;
   constexpr int WP = 64 * C;
@@ -509,8 +509,8 @@ __global__ __launch_bounds__(64 * G * W) void k_localt(
   const int64_t i0 = isub_ptr[s];
   const int ns = mode >= 1 ? (int)(isub_ptr[s + 1] - i0) : 0;
   const double* P = mbf + mbf_off[s];
-  const double* rr = rin + base * NT;
-  double* o = out + base * NT;
+  // node vectors: value (row, k) of this subdomain at vi(row, k) (see vix)
+  auto vi = [&](int row, int k) { return vix<NT>(nrows, base + row, k0 + k); };
 
   // register prefetch of the next PD tiles of a sweep: the tile of block b
   // travels through pre[b % PD] into LDS buffer b & 1 (slots and buffers
@@ -613,7 +613,7 @@ __global__ __launch_bounds__(64 * G * W) void k_localt(
   // ---- forward sweep ----
   AT T[C][NR];  // accumulators of blocks b .. b+C-1 (identical in the W waves of a group)
   auto ldr = [&](int row, int k) -> AT {
-    return (row >= 0 && row < N) ? (AT)rr[(size_t)row * NT + k0 + k] : (AT)0;
+    return (row >= 0 && row < N) ? (AT)rin[vi(row, k)] : (AT)0;
   };
 #pragma unroll
   for (int c = 0; c < C; ++c)
@@ -665,7 +665,7 @@ __global__ __launch_bounds__(64 * G * W) void k_localt(
     }
     if (w == (b % W) && j0 + lane < N)
 #pragma unroll
-      for (int k = 0; k < NR; ++k) o[(size_t)(j0 + lane) * NT + k0 + k] = (double)(y[k] * dvl);
+      for (int k = 0; k < NR; ++k) out[vi(j0 + lane, k)] = (double)(y[k] * dvl);
     // pass A: blocks b+1 .. b+C take -L_{b+c,b} y_b
     AT* by = bvec[g][1];
     wave_lds_sync();
@@ -743,7 +743,6 @@ __global__ __launch_bounds__(64 * G * W) void k_localt(
   else
     bwd_prologue(IC<0>{});
 
-  const double* qq = qv + base * NT;
   double rz[NR], qz[NR];
 #pragma unroll
   for (int k = 0; k < NR; ++k) rz[k] = qz[k] = 0.0;
@@ -752,7 +751,7 @@ __global__ __launch_bounds__(64 * G * W) void k_localt(
 #pragma unroll
   for (int k = 0; k < NR; ++k) X1[k] = X2[k] = (AT)0;
   auto ldv = [&](int row, int k) -> AT {
-    return (row >= 0 && row < N) ? (AT)o[(size_t)row * NT + k0 + k] : (AT)0;
+    return (row >= 0 && row < N) ? (AT)out[vi(row, k)] : (AT)0;
   };
 
   auto bwd_body = [&](const int b, auto parc) {
@@ -768,8 +767,8 @@ __global__ __launch_bounds__(64 * G * W) void k_localt(
       for (int q = 0; q < kPreQ; ++q) ph[q] = q < npre ? P[(size_t)q * N + row] : 0.0;
 #pragma unroll
       for (int k = 0; k < NR; ++k) {
-        rpre[k] = mode == 2 ? rr[(size_t)row * NT + k0 + k] : 0.0;
-        qpre[k] = mode == 2 ? qq[(size_t)row * NT + k0 + k] : 0.0;
+        rpre[k] = mode == 2 ? rin[vi(row, k)] : 0.0;
+        qpre[k] = mode == 2 ? qv[vi(row, k)] : 0.0;
       }
     }
     AT v[NR];
@@ -879,7 +878,7 @@ __global__ __launch_bounds__(64 * G * W) void k_localt(
       }
 #pragma unroll
       for (int k = 0; k < NR; ++k) {
-        o[(size_t)row * NT + k0 + k] = z[k];
+        out[vi(row, k)] = z[k];
         rz[k] = fma(rpre[k], z[k], rz[k]);
         qz[k] = fma(qpre[k], z[k], qz[k]);
       }
@@ -952,14 +951,14 @@ __global__ __launch_bounds__(64) void k_mbf(
 }
 
 template <int NR>
-__global__ __launch_bounds__(256) void k_bpart(const int64_t* __restrict__ sub_ptr,
+__global__ __launch_bounds__(256) void k_bpart(int64_t n, const int64_t* __restrict__ sub_ptr,
                                                const int64_t* __restrict__ isub_ptr,
                                                const int64_t* __restrict__ mbf_off,
                                                const double* __restrict__ mbf,
                                                const int64_t* __restrict__ bdst,
                                                const double* __restrict__ r, double* bpart) {
   __shared__ double lds[4 * 16];  // block sums of up to 16 values
-  bpart_sub<NR>(blockIdx.x, sub_ptr, isub_ptr, mbf_off, mbf, bdst, r, bpart, lds);
+  bpart_sub<NR>(blockIdx.x, n, sub_ptr, isub_ptr, mbf_off, mbf, bdst, r, bpart, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1040,7 +1039,7 @@ hipError_t localt_t(DeviceState& d, const double* r, double* z, const double* et
                          d.roff, d.fac_off, (const FT*)d.Lc, (const IT*)d.invd, r, z, mode,
                          d.isub_ptr, d.isub_list, d.mbf_off, d.mbf, eta, d.q, d.red.pd, off,
                          d.fuse_eta, d.Sinv, (int)d.NL, d.ldS, d.bpart, d.red.pb, d.m, init, d.sc,
-                         d.shared);
+                         d.shared, d.n);
     };
     if (bk == 0)
       go(k_localt<FT, 1, NT, G, W>);

@@ -114,13 +114,14 @@ class AlgMortar:
     """Handle of a set-up AlgMortar preconditioner (Algorithm 1) on one GPU."""
 
     def __init__(self, A, part, nparts, prec="fp64", mortar="interface", max_nrhs=1, device=0,
-                 graph=True, stream=None):
+                 graph=True, stream=None, separate_iface=False):
         lib = load()
         s, keep = _csr(A)
         p = _np(part, np.int32)
         opt = AmOptions(local_prec=_lib.PREC[prec], mortar=_lib.MORTAR[mortar],
                         max_nrhs=int(max_nrhs), device=int(device),
-                        flags=0 if graph else _lib.AM_FLAG_NO_GRAPH)
+                        flags=(0 if graph else _lib.AM_FLAG_NO_GRAPH)
+                        | (_lib.AM_FLAG_SEPARATE_IFACE if separate_iface else 0))
         h = c_void_p()
         st = c_void_p(0) if stream is False else _stream(stream)
         check(lib.algmortar_setup(byref(s), _ptr(p), int(nparts), byref(opt), st, byref(h)))

@@ -278,3 +278,20 @@ def test_pcg_16_rhs_bisect(prec):
     assert abs(info5[0]["iterations"] - infos[5]["iterations"]) <= 1
     assert rel(cpu(x5), X[5]) <= 1e-8
     h.close()
+
+
+@pytest.mark.parametrize("name", ["c1", "layered"])
+def test_separate_interface_product_parity(name):
+    """The interface solve as its own launches (row-part outer products of
+    the symmetric S^{-1}, then their sum in part order) instead of inside the
+    local kernel: apply within 1e-12 and PCG within 1e-8 of the oracle."""
+    A, part, m, b, ora = setup_case(name)
+    h = am.AlgMortar(A, part, m, separate_iface=True)
+    r = np.random.default_rng(3).standard_normal(A.n)
+    assert rel(cpu(h.apply(gpu(r))), ora.apply(r)) <= 1e-12
+    As = A.to_scipy()
+    ref = pcg(lambda v: As @ v, b, ora.apply, 1e-10)
+    x, info, _ = h.pcg(gpu(b), 1e-10)
+    assert info[0]["converged"] == 1 and abs(info[0]["iterations"] - ref.iterations) <= 1
+    assert rel(cpu(x), ref.x) <= 1e-8
+    h.close()
