@@ -48,8 +48,8 @@ def traffic_record(prec, config):
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = open(os.path.join(ROOT, "paper_2607_22905_amd", "csrc", "kernels_local.hip"), "rb").read()
-    if rec.get("kernels_local_sha256") != hashlib.sha256(src).hexdigest():
+    src = open(os.path.join(ROOT, "paper_2607_22905_amd", "csrc", "local_kernels.h"), "rb").read()
+    if rec.get("local_kernels_sha256") != hashlib.sha256(src).hexdigest():
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -152,6 +152,8 @@ def main():
     # the same kernels replayed alone (back to back, same input): context only
     iso = {}
     for name in ("local", "gemv", "spmv", "update", "bpart"):
+        if name == "gemv" and prof["gemv"][1] == 0:
+            continue  # interface solve fused into the local kernel on this handle
         ms_, by_ = h.time_kernel(name, nrhs=nrhs, reps=50 if nrhs == 1 else 10)
         iso[name] = ms_
     others = {}
@@ -168,6 +170,7 @@ def main():
     log(f"bench: in-solve launch averages: local {k_ms * 1e3:.1f} us ("
         + ", ".join(f"{k} {v['avg_launch_us']:.1f} us" for k, v in others.items())
         + f"); replayed alone: " + ", ".join(f"{k} {v * 1e3:.1f} us" for k, v in iso.items()))
+    tile_choice, tile_us = h.tile_choice(nrhs)
     traffic = traffic_record(args.prec, args.config)
     out = {
         "metric": "PCG solves/s to 1e-8 rel. residual; precond-apply HBM GB/s vs peak",
@@ -193,12 +196,13 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "kernel": "k_local (band sweeps + reconstruction)",
+                     "kernel": "k_localt (tile sweeps, fused interface solve, reconstruction)",
                      "avg_launch_us": k_ms * 1e3, "launches": k_launches,
                      "bytes_per_launch": k_bytes,
                      "timing": "HIP events around each launch of a profiled solve (plain launches)",
                      "isolated_avg_launch_us": iso["local"] * 1e3},
         "other_kernels": others,
+        "local_tile_autotune": {"choice": tile_choice, "candidate_us": tile_us},
     }
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")

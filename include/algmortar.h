@@ -22,8 +22,10 @@
  *  - Multi-RHS vectors are column-major: column c of an n x nrhs block starts
  *    at ptr + c*ld, ld >= n.
  *  - "stream" is a hipStream_t passed as void* (NULL = the null stream).
- *    algmortar_apply is asynchronous on that stream; algmortar_pcg and
- *    algmortar_adjoint_grad block until the solve ends (they report am_info).
+ *    algmortar_apply is asynchronous on that stream (except its first call
+ *    for a right-hand-side count, which runs the tile autotuner and
+ *    synchronizes); algmortar_pcg and algmortar_adjoint_grad block until the
+ *    solve ends (they report am_info).
  *  - A handle is not thread-safe; distinct handles are independent.
  */
 #ifndef ALGMORTAR_H
@@ -202,7 +204,9 @@ am_status algmortar_export_mbf(am_handle h, int64_t iface, int32_t sub, double* 
 /* Measurement: `reps` back-to-back launches of one apply kernel on the
  * handle's internal stream, bracketed by HIP events (the buffers hold the
  * last call's data).  kernel: 0 = local solves + reconstruction (the band
- * sweeps of Algorithm 2), 1 = interface solve eta = S^{-1} b (GEMV),
+ * sweeps of Algorithm 2), 1 = interface solve eta = S^{-1} b (row-part
+ * products and their sum; AM_ERR_ARG on a handle whose interface solve runs
+ * inside the local kernel),
  * 2 = interface partial right-hand sides, 3 = the PCG SpMV (p update, A p,
  * (p, Ap)), 4 = the PCG x/r update with the interface partials.  Timing 3
  * or 4 leaves the handle's PCG scalars in an unspecified state (the next
@@ -211,6 +215,16 @@ am_status algmortar_export_mbf(am_handle h, int64_t iface, int32_t sub, double* 
  * (factor, vectors and operators it must read or write once). */
 am_status algmortar_time_kernel(am_handle h, int32_t kernel, int32_t nrhs, int32_t reps,
                                 double* avg_ms, double* bytes);
+
+/* Batching form: the wave layout of the local kernel (groups of right-hand
+ * sides x column splits of each block pass) is chosen per right-hand-side
+ * count by an autotuner that times every candidate layout on this handle's
+ * subdomains.  It runs, and synchronizes, on the first algmortar_apply or
+ * algmortar_pcg with that count (or here).  choice: host (out), index of the
+ * chosen candidate; ncand: host (out), number of candidates; us: host (out,
+ * may be NULL), double[4], average launch time of each candidate in us. */
+am_status algmortar_tile_choice(am_handle h, int32_t nrhs, int32_t* choice, int32_t* ncand,
+                                double* us);
 
 /* Measurement: algmortar_pcg with plain launches (no hipGraph), every launch
  * bracketed by HIP events on the handle's internal stream and the stop flag

@@ -70,6 +70,7 @@ _SIGS = {
     "am_tpfa_face_grad": [c_void_p] * 6,
     "am_tpfa_destroy": [c_void_p],
     "algmortar_time_kernel": [c_void_p, c_int32, c_int32, c_int32, POINTER(c_double), POINTER(c_double)],
+    "algmortar_tile_choice": [c_void_p, c_int32, POINTER(c_int32), POINTER(c_int32), POINTER(c_double)],
     "algmortar_pcg_profile": [c_void_p, c_void_p, c_void_p, c_int32, c_int64, c_double, c_int32, c_void_p,
                               POINTER(c_double), POINTER(c_int64), c_void_p],
 }

@@ -522,6 +522,60 @@ static am_status check_vec_args(am_handle h, const void* a, const void* b, int32
   return AM_OK;
 }
 
+// Autotuner of the tile kernel's wave layout: for nr right-hand sides it
+// times every candidate layout (3 applies each, after one warm-up, on zeroed
+// work vectors of this handle) and keeps the fastest for the handle's later
+// applies and solves.  Runs once per right-hand-side count, outside any graph
+// capture.
+static am_status autotune_tiles(am_handle h, int nr) {
+  DeviceState& d = h->d;
+  const int slot = tile_slot(nr);
+  if (d.tile_cand[slot] >= 0) return AM_OK;
+  const int nc = tile_candidates(nr);
+  hipStream_t st = h->own;
+  HCHK(launch_fill(d.r, d.n * nr, 0.0, st));
+  HCHK(launch_fill(d.z, d.n * nr, 0.0, st));
+  if (d.NL > 0) {
+    HCHK(launch_fill(d.bpart, 2 * d.NL * nr, 0.0, st));
+    HCHK(launch_fill(d.eta, (int64_t)d.ldS * nr, 0.0, st));
+  }
+  float best = 0.f;
+  int bc = 0;
+  for (int c = 0; c < nc; ++c) {
+    d.tile_cand[slot] = c;
+    HCHK(launch_local_sweep(d, d.r, d.z, d.eta, nr, 1, st));
+    HCHK(hipEventRecord(h->ev0, st));
+    for (int i = 0; i < 3; ++i) HCHK(launch_local_sweep(d, d.r, d.z, d.eta, nr, 1, st));
+    HCHK(hipEventRecord(h->ev1, st));
+    HCHK(hipEventSynchronize(h->ev1));
+    float ms = 0.f;
+    HCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+    d.tile_us[slot][c] = ms * 1000.f / 3.f;
+    if (c == 0 || d.tile_us[slot][c] < best) {
+      best = d.tile_us[slot][c];
+      bc = c;
+    }
+  }
+  d.tile_cand[slot] = bc;
+  return AM_OK;
+}
+
+am_status algmortar_tile_choice(am_handle h, int32_t nrhs, int32_t* choice, int32_t* ncand,
+                                double* us) {
+  if (!h || !choice || !ncand || nrhs < 1 || pow2_at_least(nrhs) > h->d.max_nrhs)
+    return fail(h, AM_ERR_ARG, "bad argument");
+  HCHK(hipSetDevice(h->d.device));
+  const int nr = pow2_at_least(nrhs);
+  am_status s = autotune_tiles(h, nr);
+  if (s != AM_OK) return s;
+  const int slot = tile_slot(nr);
+  *choice = h->d.tile_cand[slot];
+  *ncand = tile_candidates(nr);
+  if (us)
+    for (int c = 0; c < *ncand; ++c) us[c] = h->d.tile_us[slot][c];
+  return AM_OK;
+}
+
 am_status algmortar_apply(am_handle h, const double* r, double* z, int32_t nrhs, int64_t ld,
                           void* stream) {
   am_status s = check_vec_args(h, r, z, nrhs, ld);
@@ -531,6 +585,11 @@ am_status algmortar_apply(am_handle h, const double* r, double* z, int32_t nrhs,
   HCHK(hipSetDevice(d.device));
   hipStream_t st = (hipStream_t)stream;
   const int nr = pow2_at_least(nrhs);
+  if (d.tile_cand[tile_slot(nr)] < 0) {
+    HCHK(hipStreamSynchronize(st));
+    am_status ts = autotune_tiles(h, nr);
+    if (ts != AM_OK) return ts;
+  }
   HCHK(launch_permute_in(d.dperm, d.n, r, ld, d.r, nrhs, st));
   if (d.NL > 0) {
     HCHK(launch_bpart(d, d.r, nr, st));
@@ -652,6 +711,10 @@ static am_status pcg_impl(am_handle h, const double* b, double* x, int32_t nrhs,
   hipStream_t st = h->own;
   const int nr = pow2_at_least(nrhs);
   const int64_t nv = d.n * nr;
+  {
+    am_status ts = autotune_tiles(h, nr);
+    if (ts != AM_OK) return ts;
+  }
   HCHK(hipEventRecord(h->ev0, st));
   HCHK(launch_permute_in(d.dperm, d.n, b, ld, d.r, nrhs, st));
   HCHK(launch_permute_in(d.dperm, d.n, b, ld, h->bp, nrhs, st));
@@ -789,6 +852,9 @@ am_status algmortar_time_kernel(am_handle h, int32_t kernel, int32_t nrhs, int32
   if (!h || !avg_ms || !bytes || reps < 1 || kernel < 0 || kernel > 4 || nrhs < 1 ||
       pow2_at_least(nrhs) > h->d.max_nrhs)
     return fail(h, AM_ERR_ARG, "bad argument");
+  if (kernel == 1 && (h->d.fuse_eta || h->d.ypart == nullptr))
+    return fail(h, AM_ERR_ARG,
+                "the interface solve of this handle runs inside the local kernel (kernel 0)");
   DeviceState& d = h->d;
   const Structure& st = h->st;
   const LocalPlan& lp = h->lp;

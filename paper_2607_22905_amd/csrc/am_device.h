@@ -64,6 +64,10 @@ struct DeviceState {
   int32_t fuse_eta = 0;  // local kernel computes its own rows of eta = S^{-1} b
   int32_t max_nrhs = 1;
   int32_t max_np = 0;       // largest padded subdomain row count
+  // wave layout of the tile kernel chosen by the autotuner per right-hand-side
+  // count (slot log2 nrhs), -1 until tuned; the timed average per candidate
+  int32_t tile_cand[5] = {-1, -1, -1, -1, -1};
+  float tile_us[5][4] = {};
 
   // device ordering and permuted matrix
   int32_t* dperm = nullptr;    // [n] device position -> original index
@@ -133,6 +137,9 @@ struct DeviceState {
 // ---- launchers (kernels_local.hip) ----
 hipError_t launch_band_factor(DeviceState& d, hipStream_t s);
 hipError_t launch_mbf(DeviceState& d, hipStream_t s);
+inline int tile_slot(int nrhs) { return nrhs <= 1 ? 0 : nrhs <= 2 ? 1 : nrhs <= 4 ? 2 : nrhs <= 8 ? 3 : 4; }
+// number of tile-kernel wave layouts the autotuner times for nrhs
+int tile_candidates(int nrhs);
 // replaces the 64 x 64 diagonal blocks of the column layout by their inverses
 hipError_t launch_invert_diag(DeviceState& d, hipStream_t s);
 // z = A_i^{-1} r (+ prolongation with eta when eta != nullptr); dots when dot_out

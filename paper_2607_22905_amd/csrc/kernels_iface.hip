@@ -392,6 +392,11 @@ static void gemv_t(DeviceState& d, hipStream_t st, int pcg, int init) {
 
 hipError_t launch_iface_gemv(DeviceState& d, int nr, int pcg, int init, hipStream_t st) {
   if (d.NL == 0 && !pcg) return hipSuccess;
+  // the part sums exist only on handles whose interface solve is not fused
+  // into the local kernel (with no interface, the launches only take the
+  // stop decision and touch no part sums)
+  if (d.NL > 0 && (d.ypart == nullptr || d.op_parts < 1 || nr > d.max_nrhs))
+    return hipErrorInvalidValue;
   switch (nr) {
     case 1: gemv_t<1>(d, st, pcg, init); break;
     case 2: gemv_t<2>(d, st, pcg, init); break;

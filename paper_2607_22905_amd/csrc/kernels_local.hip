@@ -41,6 +41,16 @@ hipError_t launch_invert_diag(DeviceState& d, hipStream_t st) {
   }
 }
 
+int tile_candidates(int nrhs) {
+  switch (tile_slot(nrhs)) {
+    case 0: return TileCands<1>::n;
+    case 1: return TileCands<2>::n;
+    case 2: return TileCands<4>::n;
+    case 3: return TileCands<8>::n;
+    default: return TileCands<16>::n;
+  }
+}
+
 hipError_t launch_local_sweep(DeviceState& d, const double* r, double* z, const double* eta,
                               int nrhs, int mode, hipStream_t st) {
   // mode >= 10: the PCG start pass (mode 2, init = 1)

@@ -1020,34 +1020,92 @@ hipError_t invert_diag_t(DeviceState& d, hipStream_t st) {
 
 // Wave layout of the tile kernel for NT right-hand sides: G groups of NT/G
 // right-hand sides, each pass split over W waves.
-template <int NT> struct TileShape {
-  static constexpr int G = NT <= 2 ? 1 : (NT == 4 ? 2 : 4);
-  static constexpr int W = NT <= 2 ? 4 : (NT == 4 ? 2 : 1);
+// Wave layouts of the tile kernel (G groups of NT/G right-hand sides, each
+// pass split over W waves): the candidates the autotuner times for each
+// right-hand-side count, the first being the default.
+template <int NT> struct TileCands;
+template <> struct TileCands<1> {
+  static constexpr int n = 2;
+  static constexpr int G[4] = {1, 1, 1, 1}, W[4] = {4, 2, 4, 4};
+};
+template <> struct TileCands<2> {
+  static constexpr int n = 2;
+  static constexpr int G[4] = {1, 2, 1, 1}, W[4] = {4, 2, 4, 4};
+};
+template <> struct TileCands<4> {
+  static constexpr int n = 3;
+  static constexpr int G[4] = {2, 4, 1, 2}, W[4] = {2, 1, 4, 2};
+};
+template <> struct TileCands<8> {
+  static constexpr int n = 3;
+  static constexpr int G[4] = {4, 2, 8, 4}, W[4] = {1, 2, 1, 1};
+};
+template <> struct TileCands<16> {
+  static constexpr int n = 3;
+  static constexpr int G[4] = {4, 8, 4, 4}, W[4] = {1, 1, 2, 1};
 };
 
-template <typename FT, int NT>
-hipError_t localt_t(DeviceState& d, const double* r, double* z, const double* eta, int mode,
-                    int init, hipStream_t st) {
+// LDS bytes of k_localt for a shape (the static arrays of the kernel)
+template <typename FT, int C, int NT, int G, int W>
+constexpr size_t tile_lds_bytes() {
+  using AT = typename AccT<FT>::T;
+  constexpr int NR = NT / G;
+  return 2 * (size_t)C * 64 * LdsPitch<FT>::v * sizeof(FT) +
+         2 * (size_t)G * (W > 1 ? W : 1) * C * (W > 1 ? 64 * NR : 1) * sizeof(AT) +
+         (size_t)TileMaxNi<NT>::v * NT * 8 + (size_t)G * W * 2 * NR * 8 +
+         (size_t)G * 2 * 64 * NR * sizeof(AT) + 64;
+}
+constexpr size_t kLdsBudget = 160 * 1024;
+
+// The shape a candidate stands for at (FT, C): the candidate where its LDS
+// fits, otherwise the default.
+template <typename FT, int C, int NT, int I> struct TileAt {
+  static constexpr int g0 = TileCands<NT>::G[I], w0 = TileCands<NT>::W[I];
+  static constexpr bool fits = tile_lds_bytes<FT, C, NT, g0, w0>() <= kLdsBudget;
+  static constexpr int G = fits ? g0 : TileCands<NT>::G[0];
+  static constexpr int W = fits ? w0 : TileCands<NT>::W[0];
+};
+
+template <typename FT, int NT, int I>
+hipError_t localt_shape(DeviceState& d, const double* r, double* z, const double* eta, int mode,
+                        int init, hipStream_t st) {
   using IT = typename AccT<FT>::T;
-  constexpr int G = TileShape<NT>::G, W = TileShape<NT>::W;
   unsigned off = 0;
   for (int bk = 0; bk < 2; ++bk) {
     const int nb = (int)d.bucket_sub[bk].size();
     if (!nb) continue;
-    auto go = [&](auto kern) {
-      hipLaunchKernelGGL(kern, dim3(nb), dim3(64 * G * W), 0, st, d.d_bucket_sub[bk], d.sub_ptr,
+    auto go = [&](auto kern, int threads) {
+      hipLaunchKernelGGL(kern, dim3(nb), dim3(threads), 0, st, d.d_bucket_sub[bk], d.sub_ptr,
                          d.roff, d.fac_off, (const FT*)d.Lc, (const IT*)d.invd, r, z, mode,
                          d.isub_ptr, d.isub_list, d.mbf_off, d.mbf, eta, d.q, d.red.pd, off,
                          d.fuse_eta, d.Sinv, (int)d.NL, d.ldS, d.bpart, d.red.pb, d.m, init, d.sc,
                          d.shared, d.n);
     };
-    if (bk == 0)
-      go(k_localt<FT, 1, NT, G, W>);
-    else
-      go(k_localt<FT, 2, NT, G, W>);
+    if (bk == 0) {
+      using S = TileAt<FT, 1, NT, I>;
+      go(k_localt<FT, 1, NT, S::G, S::W>, 64 * S::G * S::W);
+    } else {
+      using S = TileAt<FT, 2, NT, I>;
+      go(k_localt<FT, 2, NT, S::G, S::W>, 64 * S::G * S::W);
+    }
     off += nb;
   }
   return hipGetLastError();
+}
+
+template <typename FT, int NT>
+hipError_t localt_t(DeviceState& d, const double* r, double* z, const double* eta, int mode,
+                    int init, hipStream_t st) {
+  int c = d.tile_cand[tile_slot(NT)];
+  if (c < 0 || c >= TileCands<NT>::n) c = 0;
+  switch (c) {
+    case 1: return localt_shape<FT, NT, 1>(d, r, z, eta, mode, init, st);
+    case 2:
+      if constexpr (TileCands<NT>::n > 2) return localt_shape<FT, NT, 2>(d, r, z, eta, mode, init, st);
+      break;
+    default: break;
+  }
+  return localt_shape<FT, NT, 0>(d, r, z, eta, mode, init, st);
 }
 
 template <typename FT>

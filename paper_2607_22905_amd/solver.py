@@ -190,6 +190,14 @@ class AlgMortar:
         names = {0: "local", 1: "gemv", 3: "spmv", 4: "update"}
         return x, [infos[i].as_dict() for i in range(k)], {v: (ms[i], cnt[i]) for i, v in names.items()}
 
+    def tile_choice(self, nrhs=1):
+        """(chosen candidate, [average launch us of each candidate]) of the
+        local kernel's wave layout for nrhs right-hand sides (autotuned)."""
+        ch, nc = c_int32(), c_int32()
+        us = (ctypes.c_double * 4)()
+        check(load().algmortar_tile_choice(self._h, int(nrhs), byref(ch), byref(nc), us), self._h)
+        return ch.value, [us[i] for i in range(nc.value)]
+
     def time_kernel(self, kernel, nrhs=1, reps=20):
         """(average launch ms, algorithmic bytes per launch) of an apply kernel:
         "local" (band sweeps + reconstruction), "gemv", "bpart"."""

@@ -12,13 +12,16 @@ the shared input generators).
 * ``c2_pcg.json``: the 64^3 layered workload (the benchmark's): the oracle's
   apply of a seeded N(0,1) vector and its PCG solution at the workload's
   tolerance (1e-8), as norms plus values at 256 seeded cells.
+* ``c4_pcg.json``: the 128^3 precision workload: the oracle's PCG solution at
+  tol 1e-8 and at 1e-12 (the reference the reduced-precision forms are
+  measured against), values at 256 seeded cells, norms, iteration counts.
 * ``c5_adjoint.json``: the 96^3 differentiation workload: the oracle's loss
   J = 1/2 sum_obs (p - pobs)^2 (pobs from the perturbed-field forward solve),
   its adjoint gradient dJ/dlog K at 256 seeded cells and at the 20
   finite-difference cells (drawn among cells with |g| >= 1e-3 max|g|), and
   the gradient's norm and maximum.  All oracle solves at tol 1e-12.
 
-    python tests/golden/make_golden.py [structure|c2|c5]
+    python tests/golden/make_golden.py [structure|c2|c5|c4]
 """
 import hashlib
 import json
@@ -125,11 +128,34 @@ def c5_record():
     print("c5", J, res.iterations, lam_res.iterations, gmax)
 
 
+def c4_record():
+    """128^3 precision workload: the oracle's PCG solution at the workload's
+    tolerance (1e-8) and a tight reference (1e-12), as norms and values at
+    256 seeded cells, with the iteration counts."""
+    P = make_config("c4")
+    part, _ = partition_blocks(P.dims, P.partition[1])
+    pre = AlgMortarCPU(P.A, part)
+    As = P.A.to_scipy()
+    idx = np.sort(np.random.default_rng(7).choice(P.n, size=256, replace=False))
+    res = pcg(lambda v: As @ v, P.b, pre.apply, P.tol)
+    tight = pcg(lambda v: As @ v, P.b, pre.apply, 1e-12)
+    rec = dict(sample_idx=idx.tolist(), iterations=res.iterations, x_sample=res.x[idx].tolist(),
+               x_norm2=float(np.linalg.norm(res.x)), true_rel_res=res.true_rel_res, tol=P.tol,
+               tight_iterations=tight.iterations, tight_x_sample=tight.x[idx].tolist(),
+               tight_x_norm2=float(np.linalg.norm(tight.x)),
+               err_vs_tight=float(np.linalg.norm(res.x - tight.x) / np.linalg.norm(tight.x)))
+    with open(os.path.join(HERE, "c4_pcg.json"), "w") as f:
+        json.dump(rec, f, indent=1, sort_keys=True)
+    print("c4", res.iterations, tight.iterations, rec["err_vs_tight"])
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["structure", "c2", "c5"]
+    which = sys.argv[1:] or ["structure", "c2", "c5", "c4"]
     if "structure" in which:
         main()
     if "c2" in which:
         c2_record()
     if "c5" in which:
         c5_record()
+    if "c4" in which:
+        c4_record()

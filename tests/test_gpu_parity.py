@@ -295,3 +295,63 @@ def test_separate_interface_product_parity(name):
     assert info[0]["converged"] == 1 and abs(info[0]["iterations"] - ref.iterations) <= 1
     assert rel(cpu(x), ref.x) <= 1e-8
     h.close()
+
+
+def test_time_kernel_rejects_separate_interface_on_fused_handle():
+    """A handle whose interface solve runs inside the local kernel has no
+    separate interface product: timing it is refused on the host (no launch)."""
+    A, part, m, b, ora = setup_case("c1")
+    h = am.AlgMortar(A, part, m)
+    with pytest.raises(AlgMortarError) as ei:
+        h.time_kernel("gemv")
+    assert ei.value.status_name == "AM_ERR_ARG"
+    h.close()
+
+
+@pytest.mark.parametrize("separate", [False, True])
+def test_single_subdomain_pcg_one_iteration(separate):
+    """One subdomain: no interfaces, the preconditioner is A^{-1} and PCG stops
+    after one iteration (the stop decision still runs with no interface)."""
+    A, part, m, b, ora = setup_case("c1")
+    one = np.zeros(A.n, np.int32)
+    h = am.AlgMortar(A, one, 1, separate_iface=separate)
+    x, info, _ = h.pcg(gpu(b), 1e-10)
+    assert info[0]["converged"] == 1 and info[0]["iterations"] <= 2
+    xd = np.linalg.solve(A.to_scipy().toarray(), b)
+    assert rel(cpu(x), xd) <= 1e-10
+    h.close()
+
+
+def test_precision_forms_128cube():
+    """Precision form on the 128^3 workload (4096 subdomains): FP64, FP32 and
+    BF16 local factors with FP64 PCG, dots and interface solve.  Each reaches
+    the 1e-8 relative residual; its error against the oracle's tight (1e-12)
+    solution and its iteration count are compared with the FP64 form's."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c4_pcg.json")))
+    P = make_config("c4")
+    part, m = partition_blocks(P.dims, P.partition[1])
+    idx = np.array(gold["sample_idx"])
+    ref = np.array(gold["tight_x_sample"])
+    As = P.A.to_scipy()
+    rows = {}
+    for prec in ("fp64", "fp32", "bf16"):
+        h = am.AlgMortar(P.A, part, m, prec=prec)
+        x, info, _ = h.pcg(gpu(P.b), P.tol)
+        x = cpu(x)
+        h.close()
+        tr = np.linalg.norm(P.b - As @ x) / np.linalg.norm(P.b)
+        err = np.linalg.norm(x[idx] - ref) / np.linalg.norm(ref)
+        rows[prec] = (info[0]["iterations"], tr, err)
+        assert info[0]["converged"] == 1 and tr <= 2 * P.tol
+    print("\nprecision form, 128^3: prec iterations true_rel_res err_vs_oracle(1e-12 solution)")
+    for prec, (its, tr, err) in rows.items():
+        print(f"  {prec}: {its} {tr:.2e} {err:.2e}")
+    assert abs(rows["fp64"][0] - gold["iterations"]) <= 1
+    # the FP64 form's error against the tight solution is that of the tolerance
+    assert rows["fp64"][2] <= 10 * max(gold["err_vs_tight"], 1e-9)
+    for prec in ("fp32", "bf16"):
+        its, tr, err = rows[prec]
+        assert its <= rows["fp64"][0] + 10
+        assert err <= 1e-6
