@@ -728,20 +728,16 @@ __global__ __launch_bounds__(64 * G * W) void k_localt(
   }
 
   // ---- backward sweep (tiles from the last block down) ----
-  // backward: blocks from the last down, same parity convention
-  auto bwd_prologue = [&](auto parc) {
-    constexpr int par = decltype(parc)::v;  // (NB - 1) & 1
-    tile_load(NB - 1, par % PD);
-    __syncthreads();  // every wave's forward output rows are written
-    tile_store(par, par % PD);
-    if (NB > 1) tile_load(NB - 2, (par + 1) % PD);
-    if (PD == 2 && NB > 2) tile_load(NB - 3, par % PD);
-    __syncthreads();
-  };
-  if ((NB - 1) & 1)
-    bwd_prologue(IC<1>{});
-  else
-    bwd_prologue(IC<0>{});
+  // The forward sweep leaves the tiles of blocks NB-1 and NB-2 in LDS buffers
+  // (NB-1) & 1 and (NB-2) & 1, where the backward steps of those blocks read
+  // them (transposed); the ring restarts with block NB-3.
+  if (PD == 2 && NB > 2) {
+    if ((NB - 3) & 1)
+      tile_load(NB - 3, 1 % PD);
+    else
+      tile_load(NB - 3, 0);
+  }
+  __syncthreads();  // every wave's forward output rows are written
 
   double rz[NR], qz[NR];
 #pragma unroll
@@ -841,7 +837,7 @@ __global__ __launch_bounds__(64 * G * W) void k_localt(
     }
     if (b > 0) {
       constexpr int nslot = (par + 1) % PD;  // (b - 1) % PD
-      tile_store(1 - par, nslot);
+      if (b < NB - 1) tile_store(1 - par, nslot);
       if (b - 1 - PD >= 0) tile_load(b - 1 - PD, nslot);
     }
     if constexpr (W > 1) {
