@@ -14,6 +14,7 @@ structure  permutation, interface edge sets E_ij, interface numbering -- Sec. 3.
 algmortar  local operators A_i, Cholesky, MBFs, interface matrix S, apply
            -- Sec. 3.3-3.4, Algorithms 1 and 2
 pcg        preconditioned conjugate gradients -- Sec. 5, Sec. 7 set-up
+smoothing  block-Jacobi pre/post smoothing around AlgMortar -- Sec. 5.4
 adjoint    adjoint gradient dJ/dlog K of a least-squares loss (no paper analogue)
 dense      dense matrices of the operators for small-case identities -- Sec. 3-5
 
