@@ -162,6 +162,24 @@ am_status am_structure(const am_csr* A, const int32_t* part, int32_t nparts, int
 am_status algmortar_setup(const am_csr* A, const int32_t* part, int32_t nparts,
                           const am_options* opt, void* stream, am_handle* out);
 
+/* Block-Jacobi pre- and post-smoothing around the AlgMortar correction
+ * (Sec. 5.4).  After this call algmortar_apply and algmortar_pcg use
+ *   z = 0;  nu times z += B^{-1} (r - A z);  z += Mcal^{-1} (r - A z);
+ *   nu times z += B^{-1} (r - A z)
+ * with B = blockdiag(A[K, K]) over the blocks K of `blocks`, each block
+ * solved exactly (band Cholesky of the block as it is, in the handle's factor
+ * precision; the paper names block Jacobi and the number of blocks only).
+ * blocks: host int32[n], ids in [0, nblocks), none empty (typically unions of
+ * several subdomains; each block's bandwidth in ascending index order or RCM
+ * order must be at most 128).  steps: nu in [0, 1000]; 0 removes the smoother.
+ * The block factors take device memory like the subdomain factors.  Replaces
+ * any earlier smoother; synchronizes `stream` and the handle.
+ * algmortar_local_solve and algmortar_time_kernel are unaffected;
+ * algmortar_pcg_profile returns AM_ERR_UNSUPPORTED while a smoother is set.
+ * Errors: AM_ERR_ARG (partition), AM_ERR_UNSUPPORTED (bandwidth), AM_ERR_OOM. */
+am_status algmortar_set_smoother(am_handle h, const int32_t* blocks, int32_t nblocks,
+                                 int32_t steps, void* stream);
+
 /* Algorithm 2 (AlgMortarApply): z = Mcal^{-1} r for nrhs columns.
  * r, z: device, n x nrhs column-major with leading dimension ld (may not
  * alias).  Asynchronous on stream. */

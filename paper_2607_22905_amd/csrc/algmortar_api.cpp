@@ -30,6 +30,11 @@ struct am_handle_s {
   hipEvent_t evp[8] = {};                   // per-launch timing of a profiled solve
   double* tres = nullptr;  // [kMaxNRHS] ||b - Ax||^2
   double* bp = nullptr;    // permuted right-hand side
+  // block-Jacobi smoothing (Sec. 5.4): the handle of the plain diagonal
+  // blocks, the order maps and the correction buffers (owned here)
+  am_handle bj = nullptr;
+  SmoothDevice sm;
+  std::vector<void*> sm_allocs;
 };
 
 struct am_tpfa_s {
@@ -186,6 +191,8 @@ am_status algmortar_destroy(am_handle h) {
     return AM_OK;
   }
   hipSetDevice(h->d.device);
+  for (void* p : h->sm_allocs) hipFree(p);
+  if (h->bj) algmortar_destroy(h->bj);
   if (h->d.graph) hipGraphExecDestroy(h->d.graph);
   for (void* p : h->d.allocs) hipFree(p);
   if (h->d.h_flags) hipHostFree(h->d.h_flags);
@@ -200,8 +207,11 @@ am_status algmortar_destroy(am_handle h) {
   return AM_OK;
 }
 
-am_status algmortar_setup(const am_csr* A, const int32_t* part, int32_t nparts,
-                          const am_options* opt_in, void* stream, am_handle* out) {
+// plain: factor the diagonal blocks A_ii of the partition as they are (no
+// interface, no basis functions, no S): the block solves of block-Jacobi
+// smoothing (Sec. 5.4)
+static am_status setup_impl(const am_csr* A, const int32_t* part, int32_t nparts,
+                            const am_options* opt_in, void* stream, am_handle* out, bool plain) {
   if (!out) return fail(nullptr, AM_ERR_ARG, "out is null");
   *out = nullptr;
   am_options opt{AM_FP64, AM_MORTAR_PER_INTERFACE, 1, 0, 0u};
@@ -233,6 +243,15 @@ am_status algmortar_setup(const am_csr* A, const int32_t* part, int32_t nparts,
   Structure& st = h->st;
   LocalPlan& lp = h->lp;
   if ((s = build_structure(H, part, nparts, opt.mortar, st, e)) != AM_OK) { fail(h, s, e); return bail(s); }
+  if (plain) {
+    st.edge_k.clear();
+    st.edge_l.clear();
+    st.edge_a.clear();
+    st.iface_ptr.assign(1, 0);
+    st.iface_ij.clear();
+    st.isub_ptr.assign((size_t)st.m + 1, 0);
+    st.isub_list.clear();
+  }
   if ((s = plan_local(H, st, lp, e)) != AM_OK) { fail(h, s, e); return bail(s); }
   if (lp.max_ni > 128) {
     fail(h, AM_ERR_UNSUPPORTED, "a subdomain touches more than 128 mortar basis functions");
@@ -245,6 +264,7 @@ am_status algmortar_setup(const am_csr* A, const int32_t* part, int32_t nparts,
   }
 
   DeviceState& d = h->d;
+  d.plain = plain ? 1 : 0;
   d.device = opt.device;
   d.prec = opt.local_prec;
   d.n = H.n;
@@ -511,6 +531,11 @@ am_status algmortar_setup(const am_csr* A, const int32_t* part, int32_t nparts,
 #undef SCHK
 }
 
+am_status algmortar_setup(const am_csr* A, const int32_t* part, int32_t nparts,
+                          const am_options* opt_in, void* stream, am_handle* out) {
+  return setup_impl(A, part, nparts, opt_in, stream, out, false);
+}
+
 // ---------------------------------------------------------------------------
 static am_status check_vec_args(am_handle h, const void* a, const void* b, int32_t nrhs,
                                 int64_t ld) {
@@ -576,6 +601,108 @@ am_status algmortar_tile_choice(am_handle h, int32_t nrhs, int32_t* choice, int3
   return AM_OK;
 }
 
+static void drop_smoother(am_handle h) {
+  for (void* p : h->sm_allocs) hipFree(p);
+  h->sm_allocs.clear();
+  if (h->bj) algmortar_destroy(h->bj);
+  h->bj = nullptr;
+  h->sm = SmoothDevice{};
+}
+
+am_status algmortar_set_smoother(am_handle h, const int32_t* blocks, int32_t nblocks,
+                                 int32_t steps, void* stream) {
+  if (!h) return fail(nullptr, AM_ERR_ARG, "null handle");
+  if (steps < 0 || steps > 1000) return fail(h, AM_ERR_ARG, "steps must be in [0, 1000]");
+  DeviceState& d = h->d;
+  HCHK(hipSetDevice(d.device));
+  if (stream) HCHK(hipStreamSynchronize((hipStream_t)stream));
+  HCHK(hipStreamSynchronize(h->own));
+  drop_smoother(h);
+  if (steps == 0) return AM_OK;
+  if (!blocks) return fail(h, AM_ERR_ARG, "null block partition");
+  std::string e;
+  am_status s = validate_partition(d.n, blocks, nblocks, e);
+  if (s != AM_OK) return fail(h, s, e);
+  // A in the original order, from the device copy (ELL rows in device order;
+  // padding entries sit on the row's own column with value 0, which the
+  // positive diagonal never has)
+  const int64_t n = d.n;
+  const int32_t w = d.ell_w;
+  std::vector<int32_t> ec((size_t)w * n);
+  std::vector<double> ev((size_t)w * n);
+  HCHK(hipMemcpy(ec.data(), d.ell_col, sizeof(int32_t) * ec.size(), hipMemcpyDeviceToHost));
+  HCHK(hipMemcpy(ev.data(), d.ell_val, sizeof(double) * ev.size(), hipMemcpyDeviceToHost));
+  const std::vector<int32_t>& dperm = h->lp.dperm;
+  const std::vector<int32_t>& dpos = h->lp.dpos;
+  std::vector<int64_t> rp((size_t)n + 1, 0);
+  for (int64_t i = 0; i < n; ++i)
+    for (int32_t c = 0; c < w; ++c) {
+      const int32_t col = ec[(size_t)c * n + i];
+      if (!(col == i && ev[(size_t)c * n + i] == 0.0)) rp[dperm[i] + 1] += 1;
+    }
+  for (int64_t o = 0; o < n; ++o) rp[o + 1] += rp[o];
+  std::vector<int32_t> ci((size_t)rp[n]);
+  std::vector<double> cv((size_t)rp[n]);
+  {
+    std::vector<std::pair<int32_t, double>> row;
+    for (int64_t i = 0; i < n; ++i) {
+      row.clear();
+      for (int32_t c = 0; c < w; ++c) {
+        const int32_t col = ec[(size_t)c * n + i];
+        const double v = ev[(size_t)c * n + i];
+        if (!(col == i && v == 0.0)) row.emplace_back(dperm[col], v);
+      }
+      std::sort(row.begin(), row.end(),
+                [](const std::pair<int32_t, double>& a, const std::pair<int32_t, double>& b) {
+                  return a.first < b.first;
+                });
+      const int64_t o = dperm[i];
+      for (size_t t = 0; t < row.size(); ++t) {
+        ci[rp[o] + t] = row[t].first;
+        cv[rp[o] + t] = row[t].second;
+      }
+    }
+  }
+  am_csr A{n, rp[n], rp.data(), ci.data(), cv.data(), 0};
+  am_options o = h->opt;
+  o.mortar = AM_MORTAR_PER_INTERFACE;
+  am_handle bj = nullptr;
+  s = setup_impl(&A, blocks, nblocks, &o, nullptr, &bj, true);
+  if (s != AM_OK) return fail(h, s, std::string("smoothing blocks: ") + algmortar_last_error(nullptr));
+  h->bj = bj;
+  std::vector<int32_t> to_bj((size_t)n), to_am((size_t)n);
+  for (int64_t i = 0; i < n; ++i) {
+    to_bj[i] = dpos[bj->lp.dperm[i]];
+    to_am[i] = bj->lp.dpos[dperm[i]];
+  }
+  int32_t *d_to_bj = nullptr, *d_to_am = nullptr;
+  double *t_am = nullptr, *w_am = nullptr;
+  auto grab = [&](void** p, size_t bytes) -> hipError_t {
+    hipError_t he = hipMalloc(p, bytes);
+    if (he == hipSuccess) h->sm_allocs.push_back(*p);
+    return he;
+  };
+  const size_t nv = (size_t)n * d.max_nrhs;
+  hipError_t he;
+  if ((he = grab((void**)&d_to_bj, sizeof(int32_t) * n)) != hipSuccess ||
+      (he = grab((void**)&d_to_am, sizeof(int32_t) * n)) != hipSuccess ||
+      (he = grab((void**)&t_am, sizeof(double) * nv)) != hipSuccess ||
+      (he = grab((void**)&w_am, sizeof(double) * nv)) != hipSuccess ||
+      (he = hipMemcpy(d_to_bj, to_bj.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice)) != hipSuccess ||
+      (he = hipMemcpy(d_to_am, to_am.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice)) != hipSuccess) {
+    drop_smoother(h);
+    return fail(h, he == hipErrorOutOfMemory ? AM_ERR_OOM : AM_ERR_HIP,
+                std::string("smoother buffers: ") + hipGetErrorString(he));
+  }
+  h->sm.bj = &bj->d;
+  h->sm.steps = steps;
+  h->sm.to_bj = d_to_bj;
+  h->sm.to_am = d_to_am;
+  h->sm.t_am = t_am;
+  h->sm.w_am = w_am;
+  return AM_OK;
+}
+
 am_status algmortar_apply(am_handle h, const double* r, double* z, int32_t nrhs, int64_t ld,
                           void* stream) {
   am_status s = check_vec_args(h, r, z, nrhs, ld);
@@ -590,12 +717,21 @@ am_status algmortar_apply(am_handle h, const double* r, double* z, int32_t nrhs,
     am_status ts = autotune_tiles(h, nr);
     if (ts != AM_OK) return ts;
   }
-  HCHK(launch_permute_in(d.dperm, d.n, r, ld, d.r, nrhs, st));
-  if (d.NL > 0) {
-    HCHK(launch_bpart(d, d.r, nr, st));
-    if (!d.fuse_eta) HCHK(launch_iface_gemv(d, nr, 0, 0, st));
+  if (h->sm.steps > 0 && h->bj->d.tile_cand[tile_slot(nr)] < 0) {
+    HCHK(hipStreamSynchronize(st));
+    am_status ts = autotune_tiles(h->bj, nr);
+    if (ts != AM_OK) return fail(h, ts, h->bj->err);
   }
-  HCHK(launch_local_sweep(d, d.r, d.z, d.eta, nr, 1, st));
+  HCHK(launch_permute_in(d.dperm, d.n, r, ld, d.r, nrhs, st));
+  if (h->sm.steps > 0) {
+    HCHK(launch_smoothed_apply(d, h->sm, d.r, d.z, nr, st));
+  } else {
+    if (d.NL > 0) {
+      HCHK(launch_bpart(d, d.r, nr, st));
+      if (!d.fuse_eta) HCHK(launch_iface_gemv(d, nr, 0, 0, st));
+    }
+    HCHK(launch_local_sweep(d, d.r, d.z, d.eta, nr, 1, st));
+  }
   HCHK(launch_permute_out(d.dperm, d.n, d.z, z, ld, nrhs, st));
   return AM_OK;
 }
@@ -704,6 +840,9 @@ static am_status pcg_impl(am_handle h, const double* b, double* x, int32_t nrhs,
   if (s != AM_OK) return s;
   if (!(tol > 0.0) || !(tol < 1.0)) return fail(h, AM_ERR_ARG, "tol must be in (0, 1)");
   if (maxit <= 0) maxit = 10000;
+  const bool smooth = h->sm.steps > 0;
+  if (smooth && prof)
+    return fail(h, AM_ERR_UNSUPPORTED, "the profiled solve does not cover block-Jacobi smoothing");
   if (nrhs == 1) ld = h->d.n;
   DeviceState& d = h->d;
   HCHK(hipSetDevice(d.device));
@@ -714,6 +853,7 @@ static am_status pcg_impl(am_handle h, const double* b, double* x, int32_t nrhs,
   {
     am_status ts = autotune_tiles(h, nr);
     if (ts != AM_OK) return ts;
+    if (smooth && (ts = autotune_tiles(h->bj, nr)) != AM_OK) return fail(h, ts, h->bj->err);
   }
   HCHK(hipEventRecord(h->ev0, st));
   HCHK(launch_permute_in(d.dperm, d.n, b, ld, d.r, nrhs, st));
@@ -725,6 +865,28 @@ static am_status pcg_impl(am_handle h, const double* b, double* x, int32_t nrhs,
   HCHK(launch_fill(d.p[1], nv, 0.0, st));
   HCHK(launch_fill(d.eta, (int64_t)std::max<int32_t>(d.ldS, 1) * nr, 0.0, st));
   HCHK(launch_pcg_init(d, nr, tol, maxit, d.prec != AM_FP64 ? 1 : 0, st));
+  if (smooth) {
+    // Smoothed preconditioner (some 4 nu + 10 launches per apply): plain
+    // launches, and the stop flag is read after each stop test so that no
+    // apply runs after convergence.
+    auto stopped = [&](int init) -> hipError_t {
+      hipError_t e = launch_stop_test(d, nr, init, st);
+      if (e != hipSuccess) return e;
+      if ((e = hipMemcpyAsync(d.h_flags, &d.shared->all_done, sizeof(int32_t),
+                              hipMemcpyDeviceToHost, st)) != hipSuccess)
+        return e;
+      return hipStreamSynchronize(st);
+    };
+    HCHK(launch_pcg_rr0(d, nr, st));
+    HCHK(stopped(1));
+    for (int it = 0; !d.h_flags[0] && it <= maxit + 1; ++it) {
+      HCHK(launch_smoothed_apply(d, h->sm, d.r, d.z, nr, st));
+      HCHK(launch_smooth_dots(d, nr, st));
+      HCHK(launch_pcg_spmv(d, nr, it & 1, st));
+      HCHK(launch_pcg_update(d, nr, it & 1, st));
+      HCHK(stopped(0));
+    }
+  } else {
   HCHK(launch_pcg_start(d, nr, st));
   const bool use_graph = !(h->opt.flags & AM_FLAG_NO_GRAPH) && !prof;
   if (use_graph && (d.graph == nullptr || d.graph_nrhs != nr)) {
@@ -767,6 +929,7 @@ static am_status pcg_impl(am_handle h, const double* b, double* x, int32_t nrhs,
       HCHK(hipEventSynchronize(h->evf[(c - 1) & 1]));
       if (d.h_flags[(c - 1) & 1]) break;
     }
+  }
   }
   HCHK(launch_permute_out(d.dperm, d.n, d.x, x, ld, nrhs, st));
   HCHK(hipEventRecord(h->ev1, st));

@@ -62,6 +62,7 @@ struct DeviceState {
   int64_t NL = 0, NE = 0;
   int32_t ldS = 0;  // padded interface dimension (multiple of kTile)
   int32_t fuse_eta = 0;  // local kernel computes its own rows of eta = S^{-1} b
+  int32_t plain = 0;     // factors are the plain diagonal blocks A_ii (block Jacobi)
   int32_t max_nrhs = 1;
   int32_t max_np = 0;       // largest padded subdomain row count
   // wave layout of the tile kernel chosen by the autotuner per right-hand-side
@@ -168,6 +169,25 @@ hipError_t launch_pcg_spmv(DeviceState& d, int nrhs, int parity, hipStream_t s);
 hipError_t launch_pcg_update(DeviceState& d, int nrhs, int parity, hipStream_t s);
 hipError_t launch_true_residual(DeviceState& d, const double* bperm, int nrhs, double* out2,
                                 hipStream_t s);
+
+hipError_t launch_pcg_rr0(DeviceState& d, int nrhs, hipStream_t s);  // ||r_0||^2 partials, b(r_0)
+// the stop test on the ||r||^2 partials of the last update (kernels_local.hip)
+hipError_t launch_stop_test(DeviceState& d, int nrhs, int init, hipStream_t s);
+
+// ---- block-Jacobi smoothing (kernels_smooth.hip) ----
+struct SmoothDevice {
+  DeviceState* bj = nullptr;        // band factors of the plain diagonal blocks
+  int32_t steps = 0;                // steps before and after the correction
+  const int32_t* to_bj = nullptr;   // [n] AlgMortar position of each block-Jacobi position
+  const int32_t* to_am = nullptr;   // [n] block-Jacobi position of each AlgMortar position
+  double* t_am = nullptr;           // [n * max_nrhs] correction input, AlgMortar order
+  double* w_am = nullptr;           // [n * max_nrhs] correction output
+};
+// z_am = M^{-1} r_am (both in d's device order, node vectors of nr columns)
+hipError_t launch_smoothed_apply(DeviceState& d, SmoothDevice& sm, const double* r_am,
+                                 double* z_am, int nr, hipStream_t s);
+// (r, z) and (q, z) partials of d's PCG vectors into d.red.pd (m workgroups)
+hipError_t launch_smooth_dots(DeviceState& d, int nrhs, hipStream_t s);
 
 // ---- launchers (kernels_tpfa.hip) ----
 struct TpfaDevice {

@@ -76,4 +76,24 @@ hipError_t launch_bpart(DeviceState& d, const double* r, int nrhs, hipStream_t s
   return hipGetLastError();
 }
 
+// The stop test of a PCG iteration as a launch of its own (one wave): used
+// where the preconditioner is not the local kernel itself.
+template <int NR>
+__global__ __launch_bounds__(64) void k_stop(const double* __restrict__ pb, int npb, int init,
+                                             PcgScalars* sc, PcgShared* sh) {
+  stop_test<NR>(pb, npb, init, sc, sh);
+}
+
+hipError_t launch_stop_test(DeviceState& d, int nr, int init, hipStream_t st) {
+  switch (nr) {
+    case 1: hipLaunchKernelGGL(k_stop<1>, dim3(1), dim3(64), 0, st, d.red.pb, d.m, init, d.sc, d.shared); break;
+    case 2: hipLaunchKernelGGL(k_stop<2>, dim3(1), dim3(64), 0, st, d.red.pb, d.m, init, d.sc, d.shared); break;
+    case 4: hipLaunchKernelGGL(k_stop<4>, dim3(1), dim3(64), 0, st, d.red.pb, d.m, init, d.sc, d.shared); break;
+    case 8: hipLaunchKernelGGL(k_stop<8>, dim3(1), dim3(64), 0, st, d.red.pb, d.m, init, d.sc, d.shared); break;
+    case 16: hipLaunchKernelGGL(k_stop<16>, dim3(1), dim3(64), 0, st, d.red.pb, d.m, init, d.sc, d.shared); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 }  // namespace am

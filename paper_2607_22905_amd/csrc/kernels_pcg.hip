@@ -497,6 +497,10 @@ hipError_t launch_pcg_start(DeviceState& d, int nr, hipStream_t s) {
   return launch_local_sweep(d, d.r, d.z, d.eta, nr, 12, s);
 }
 
+hipError_t launch_pcg_rr0(DeviceState& d, int nr, hipStream_t s) {
+  return update_xr(d, nr, 0, 1, s);
+}
+
 hipError_t launch_pcg_spmv(DeviceState& d, int nr, int parity, hipStream_t s) {
   const double* po = d.p[parity];
   double* pn = d.p[1 - parity];

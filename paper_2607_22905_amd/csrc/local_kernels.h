@@ -60,7 +60,7 @@ __global__ __launch_bounds__(256) void k_band_factor(
     const int64_t* __restrict__ roff, const int64_t* __restrict__ fac_off,
     const int64_t* __restrict__ prp, const int32_t* __restrict__ pci,
     const double* __restrict__ pv, FT* __restrict__ Lc, FT* __restrict__ Lr,
-    typename AccT<FT>::T* __restrict__ invd, int32_t* __restrict__ fail) {
+    typename AccT<FT>::T* __restrict__ invd, int32_t* __restrict__ fail, int plain) {
   using IT = typename AccT<FT>::T;
   constexpr int WN = WP + 1;
   __shared__ double B[WN * WN];
@@ -76,7 +76,8 @@ __global__ __launch_bounds__(256) void k_band_factor(
   const int tid = threadIdx.x;
 
   // row `row` of A_i: in-subdomain lower entries, minus the sum of the
-  // couplings that leave the subdomain on the diagonal
+  // couplings that leave the subdomain on the diagonal (plain: the diagonal
+  // block A_ii itself, for block-Jacobi smoothing)
   auto load_row = [&](int row) {
     const int64_t g = base + row;
     double dout = 0.0;
@@ -91,7 +92,7 @@ __global__ __launch_bounds__(256) void k_band_factor(
         dout += v;
       }
     }
-    Br[row % WN] -= dout;
+    if (!plain) Br[row % WN] -= dout;
   };
 
   for (int t = tid; t < WN * WN; t += blockDim.x) B[t] = 0.0;
@@ -969,11 +970,11 @@ hipError_t band_factor_t(DeviceState& d, hipStream_t st) {
     if (bk == 0)
       hipLaunchKernelGGL((k_band_factor<FT, 64>), dim3(nb), dim3(256), 0, st,
                          d.d_bucket_sub[bk], d.sub_ptr, d.roff, d.fac_off, d.prp, d.pci, d.pv,
-                         (FT*)d.Lc, (FT*)d.Lr, (IT*)d.invd, d.fail);
+                         (FT*)d.Lc, (FT*)d.Lr, (IT*)d.invd, d.fail, d.plain);
     else
       hipLaunchKernelGGL((k_band_factor<FT, 128>), dim3(nb), dim3(256), 0, st,
                          d.d_bucket_sub[bk], d.sub_ptr, d.roff, d.fac_off, d.prp, d.pci, d.pv,
-                         (FT*)d.Lc, (FT*)d.Lr, (IT*)d.invd, d.fail);
+                         (FT*)d.Lc, (FT*)d.Lr, (IT*)d.invd, d.fail, d.plain);
   }
   return hipGetLastError();
 }

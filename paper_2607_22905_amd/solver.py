@@ -144,8 +144,19 @@ class AlgMortar:
         except Exception:
             pass
 
+    def set_smoother(self, blocks, nblocks, steps, stream=None):
+        """Block-Jacobi pre/post smoothing (Sec. 5.4) on the blocks of the
+        host partition ``blocks`` (int32[n]), ``steps`` before and after the
+        correction; steps = 0 removes it."""
+        b = _np(blocks, np.int32)
+        if b.shape != (self.n,):
+            raise ValueError("blocks must have one entry per unknown")
+        check(load().algmortar_set_smoother(self._h, _ptr(b), int(nblocks), int(steps),
+                                            _stream(stream)), self._h)
+        self.smooth_steps = int(steps)
+
     def apply(self, r, out=None, stream=None):
-        """z = Mcal^{-1} r (Algorithm 2)."""
+        """z = Mcal^{-1} r (Algorithm 2), smoothed when a smoother is set."""
         import torch
         k = _vec(r, self.n)
         z = torch.empty_like(r) if out is None else out
