@@ -54,11 +54,13 @@ def traffic_record(prec, config):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(P, part, iters, its_to_converge):
+def cpu_baseline(P, part, iters, its_to_converge, smooth=None):
     """The FP64 oracle on the host cores: set-up (untimed for the metric),
-    then a bounded sample of PCG iterations, extrapolated to a whole solve."""
+    then a bounded sample of PCG iterations, extrapolated to a whole solve.
+    smooth: (blocks, steps) for the block-Jacobi-smoothed preconditioner."""
     import numpy as np
     from oracle import AlgMortarCPU, pcg
+    from oracle.smoothing import SmoothedAlgMortarCPU
     try:
         from threadpoolctl import threadpool_info
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
@@ -66,6 +68,8 @@ def cpu_baseline(P, part, iters, its_to_converge):
         threads = os.cpu_count()
     t0 = time.perf_counter()
     pre = AlgMortarCPU(P.A, part)
+    if smooth is not None:
+        pre = SmoothedAlgMortarCPU(pre, smooth[0], smooth[1])
     t_setup = time.perf_counter() - t0
     As = P.A.to_scipy()
     t0 = time.perf_counter()
@@ -90,6 +94,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=12)
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--smooth-steps", type=int, default=0,
+                    help="block-Jacobi steps before and after the AlgMortar correction (Sec. 5.4)")
+    ap.add_argument("--smooth-blocks", default="8,8,32",
+                    help="block sizes bx,by,bz of the smoothing partition (Cartesian workloads)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -124,6 +132,14 @@ def main():
     t0 = time.perf_counter()
     nrhs = P.nrhs
     h = am.AlgMortar(P.A, part, m, prec=args.prec, graph=not args.no_graph, max_nrhs=nrhs)
+    smooth = None
+    if args.smooth_steps > 0:
+        if P.partition[0] != "blocks":
+            sys.exit("bench.py: --smooth-steps needs a Cartesian (block-partitioned) workload")
+        sb = tuple(int(v) for v in args.smooth_blocks.split(","))
+        blocks, nb = am.partition_blocks(P.dims, sb)
+        h.set_smoother(blocks, nb, args.smooth_steps)
+        smooth = (blocks, args.smooth_steps)
     torch.cuda.synchronize()
     setup_ms = (time.perf_counter() - t0) * 1e3
     # right-hand sides as rows of a (k, n) block (column c of the C-ABI's n x k block)
@@ -145,10 +161,17 @@ def main():
     # Kernel durations inside a solve: one more solve of the same system with
     # every launch bracketed by HIP events on the library's stream (plain
     # launches instead of the graph; same kernels, order, data and cache state).
-    _, pinfo, prof = h.pcg_profile(b, P.tol, out=x)
-    k_ms_total, k_launches = prof["local"]
-    k_ms = k_ms_total / max(k_launches, 1)
-    _, k_bytes = h.time_kernel("local", nrhs=nrhs, reps=1)
+    if smooth is None:
+        _, pinfo, prof = h.pcg_profile(b, P.tol, out=x)
+        k_ms_total, k_launches = prof["local"]
+        k_ms = k_ms_total / max(k_launches, 1)
+        _, k_bytes = h.time_kernel("local", nrhs=nrhs, reps=1)
+    else:
+        # the smoothed solve has no event-timed form: the dominant kernel (the
+        # block solves, 2 nu launches per iteration) is timed replayed alone
+        prof = {"local": (0.0, 0), "gemv": (0.0, 0), "spmv": (0.0, 0), "update": (0.0, 0)}
+        k_ms, k_bytes = h.time_kernel("smooth_block", nrhs=nrhs, reps=20)
+        k_launches = 2 * args.smooth_steps * its
     # the same kernels replayed alone (back to back, same input): context only
     iso = {}
     for name in ("local", "gemv", "spmv", "update", "bpart"):
@@ -171,7 +194,7 @@ def main():
         + ", ".join(f"{k} {v['avg_launch_us']:.1f} us" for k, v in others.items())
         + f"); replayed alone: " + ", ".join(f"{k} {v * 1e3:.1f} us" for k, v in iso.items()))
     tile_choice, tile_us = h.tile_choice(nrhs)
-    traffic = traffic_record(args.prec, args.config)
+    traffic = traffic_record(args.prec, args.config) if smooth is None else None
     out = {
         "metric": "PCG solves/s to 1e-8 rel. residual; precond-apply HBM GB/s vs peak",
         "value": args.steps * nrhs / elapsed,
@@ -188,7 +211,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {WORKLOADS.get(args.config, args.config)}",
                    "n": P.n, "subdomains": m, "interfaces": h.n_iface, "tol": P.tol,
-                   "local_prec": args.prec, "parallelism": "single GPU"},
+                   "local_prec": args.prec, "parallelism": "single GPU",
+                   **({"smooth_steps": args.smooth_steps, "smooth_blocks": args.smooth_blocks}
+                      if smooth is not None else {})},
         "iterations": its,
         "true_rel_res": max(i["true_rel_res"] for i in infos[-1]),
         "setup_ms": setup_ms,
@@ -196,17 +221,20 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "kernel": "k_localt (tile sweeps, fused interface solve, reconstruction)",
+                     "kernel": ("k_localt (tile sweeps, fused interface solve, reconstruction)"
+                                if smooth is None else
+                                "k_localt on the smoothing blocks (block-Jacobi solves)"),
                      "avg_launch_us": k_ms * 1e3, "launches": k_launches,
                      "bytes_per_launch": k_bytes,
-                     "timing": "HIP events around each launch of a profiled solve (plain launches)",
+                     "timing": ("HIP events around each launch of a profiled solve (plain launches)"
+                                if smooth is None else "replayed alone (20 back-to-back launches)"),
                      "isolated_avg_launch_us": iso["local"] * 1e3},
         "other_kernels": others,
         "local_tile_autotune": {"choice": tile_choice, "candidate_us": tile_us},
     }
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(P, part, args.cpu_iters, its)
+        out["cpu_baseline"] = cpu_baseline(P, part, args.cpu_iters, its, smooth)
     else:
         out["cpu_baseline"] = None
     h.close()

@@ -176,7 +176,8 @@ am_status algmortar_setup(const am_csr* A, const int32_t* part, int32_t nparts,
  * any earlier smoother; synchronizes `stream` and the handle.
  * algmortar_local_solve and algmortar_time_kernel are unaffected;
  * algmortar_pcg_profile returns AM_ERR_UNSUPPORTED while a smoother is set.
- * Errors: AM_ERR_ARG (partition), AM_ERR_UNSUPPORTED (bandwidth), AM_ERR_OOM. */
+ * Errors: AM_ERR_ARG (partition), AM_ERR_UNSUPPORTED (bandwidth), AM_ERR_OOM;
+ * after an error the handle has no smoother. */
 am_status algmortar_set_smoother(am_handle h, const int32_t* blocks, int32_t nblocks,
                                  int32_t steps, void* stream);
 
@@ -226,9 +227,11 @@ am_status algmortar_export_mbf(am_handle h, int64_t iface, int32_t sub, double* 
  * products and their sum; AM_ERR_ARG on a handle whose interface solve runs
  * inside the local kernel),
  * 2 = interface partial right-hand sides, 3 = the PCG SpMV (p update, A p,
- * (p, Ap)), 4 = the PCG x/r update with the interface partials.  Timing 3
- * or 4 leaves the handle's PCG scalars in an unspecified state (the next
- * algmortar_pcg call re-initialises them).  avg_ms: host (out), average launch
+ * (p, Ap)), 4 = the PCG x/r update with the interface partials, 5 = the
+ * block solves of the smoother set by algmortar_set_smoother (kernel 0 on the
+ * block factors; AM_ERR_ARG without a smoother).  Timing 3 or 4 leaves the
+ * handle's PCG scalars in an unspecified state (the next algmortar_pcg call
+ * re-initialises them).  avg_ms: host (out), average launch
  * duration; bytes: host (out), the kernel's algorithmic HBM bytes per launch
  * (factor, vectors and operators it must read or write once). */
 am_status algmortar_time_kernel(am_handle h, int32_t kernel, int32_t nrhs, int32_t reps,

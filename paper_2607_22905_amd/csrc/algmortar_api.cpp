@@ -1012,9 +1012,16 @@ am_status algmortar_export_mbf(am_handle h, int64_t iface, int32_t sub, double* 
 
 am_status algmortar_time_kernel(am_handle h, int32_t kernel, int32_t nrhs, int32_t reps,
                                 double* avg_ms, double* bytes) {
-  if (!h || !avg_ms || !bytes || reps < 1 || kernel < 0 || kernel > 4 || nrhs < 1 ||
+  if (!h || !avg_ms || !bytes || reps < 1 || kernel < 0 || kernel > 5 || nrhs < 1 ||
       pow2_at_least(nrhs) > h->d.max_nrhs)
     return fail(h, AM_ERR_ARG, "bad argument");
+  if (kernel == 5) {  // the smoother's block solves: kernel 0 of the block factors
+    if (!h->bj) return fail(h, AM_ERR_ARG, "no smoother is set");
+    HCHK(hipSetDevice(h->d.device));
+    am_status ts = autotune_tiles(h->bj, pow2_at_least(nrhs));
+    if (ts == AM_OK) ts = algmortar_time_kernel(h->bj, 0, nrhs, reps, avg_ms, bytes);
+    return ts == AM_OK ? AM_OK : fail(h, ts, h->bj->err);
+  }
   if (kernel == 1 && (h->d.fuse_eta || h->d.ypart == nullptr))
     return fail(h, AM_ERR_ARG,
                 "the interface solve of this handle runs inside the local kernel (kernel 0)");

@@ -212,7 +212,7 @@ class AlgMortar:
     def time_kernel(self, kernel, nrhs=1, reps=20):
         """(average launch ms, algorithmic bytes per launch) of an apply kernel:
         "local" (band sweeps + reconstruction), "gemv", "bpart"."""
-        kid = {"local": 0, "gemv": 1, "bpart": 2, "spmv": 3, "update": 4}[kernel]
+        kid = {"local": 0, "gemv": 1, "bpart": 2, "spmv": 3, "update": 4, "smooth_block": 5}[kernel]
         ms, by = ctypes.c_double(), ctypes.c_double()
         check(load().algmortar_time_kernel(self._h, kid, int(nrhs), int(reps), byref(ms), byref(by)), self._h)
         return ms.value, by.value
