@@ -32,6 +32,8 @@ WORKLOADS = {
           "1 RHS, PCG tol 1e-8",
     "c1": "64x64 K = exp(GRF), TPFA 5-point, 16 subdomains of 16^2, 1 RHS, PCG tol 1e-10",
     "c5": "96^3 ln K GRF sigma 2, TPFA 7-point, 1728 subdomains of 8^3, 1 RHS, PCG tol 1e-10",
+    "c6": "64^3 periodic cross pattern, kappa 1e6 on 2-cell channels through every 8^3 tile, "
+          "p fixed on the y faces, TPFA 7-point, 512 subdomains of 8^3, 1 RHS, PCG tol 1e-8",
     "c3": "128x128x64 distorted hexahedra, ln K GRF sigma 2, recursive bisection into "
           "200-800-cell subdomains, 16 RHS (well pairs) solved together, PCG tol 1e-8",
 }
@@ -94,6 +96,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=12)
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--theta", type=float, default=None,
+                    help="contrast sweep K -> K^theta (c2, c6)")
     ap.add_argument("--smooth-steps", type=int, default=0,
                     help="block-Jacobi steps before and after the AlgMortar correction (Sec. 5.4)")
     ap.add_argument("--smooth-blocks", default="8,8,32",
@@ -120,7 +124,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     log(f"bench: building workload {args.config}")
-    P = make_config(args.config)
+    P = make_config(args.config) if args.theta is None else make_config(args.config, theta=args.theta)
     if P.partition[0] == "blocks":
         part, m = am.partition_blocks(P.dims, P.partition[1])
     else:
@@ -212,6 +216,7 @@ def main():
         "config": {"workload": f"{args.config}: {WORKLOADS.get(args.config, args.config)}",
                    "n": P.n, "subdomains": m, "interfaces": h.n_iface, "tol": P.tol,
                    "local_prec": args.prec, "parallelism": "single GPU",
+                   **({"theta": args.theta} if args.theta is not None else {}),
                    **({"smooth_steps": args.smooth_steps, "smooth_blocks": args.smooth_blocks}
                       if smooth is not None else {})},
         "iterations": its,

@@ -87,3 +87,42 @@ def test_distorted_hex_positive_and_mmatrix():
     assert f.gk.min() > 0
     A, _ = assemble(f, np.exp(np.random.default_rng(0).normal(size=240)), 240)
     _check_mmatrix(A)
+
+
+def test_cross_pattern_closed_forms():
+    """The cross pattern: in every 8^3 tile, cells with at least two of three
+    tile coordinates in {3, 4} -- 3 bars of 2x2x8 sharing a 2^3 core, so
+    3*32 - 2*8 = 80 cells; kappa in {1, 1e6}; straight channels along x, y
+    and z cross the whole grid; the tile is symmetric under a -> 7 - a."""
+    from workloads.fields import cross_log_kappa
+    lk = cross_log_kappa(24, 16, 8)
+    assert set(np.unique(lk)) == {0.0, math.log(1e6)}
+    hi = lk > 0
+    assert hi.sum() == 80 * (3 * 2 * 1)
+    t = hi[:8, :8, :8]
+    assert np.array_equal(t, t[::-1, :, :]) and np.array_equal(t, t[:, ::-1, :])
+    assert np.array_equal(t, t[:, :, ::-1]) and np.array_equal(t, np.transpose(t, (1, 0, 2)))
+    assert hi[3:5, 3:5, :].all() and hi[3:5, :, 3:5].all() and hi[:, 3:5, 3:5].all()
+    # a cell off every band is low
+    assert not hi[0, 0, 0] and not hi[3, 0, 0]
+
+
+def test_contrast_sweep_scales_the_contrast():
+    """K -> K^theta turns a field of contrast c into one of contrast c^theta."""
+    P1 = make_config("c6", nx=16, ny=16, nz=16)
+    for th in (0.6, 1.4):
+        P = make_config("c6", nx=16, ny=16, nz=16, theta=th)
+        K = np.exp(P.logK)
+        assert math.isclose(K.max() / K.min(), 1e6 ** th, rel_tol=1e-12)
+        assert np.allclose(P.logK, th * P1.logK, rtol=0, atol=0)
+    Pl1 = make_config("c2", nx=16, ny=16, nz=16)
+    Pl = make_config("c2", nx=16, ny=16, nz=16, theta=1.4)
+    c1 = np.exp(Pl1.logK).max() / np.exp(Pl1.logK).min()
+    c = np.exp(Pl.logK).max() / np.exp(Pl.logK).min()
+    assert math.isclose(c, c1 ** 1.4, rel_tol=1e-9)
+
+
+def test_cross_config_is_spd_mmatrix():
+    P = make_config("c6", nx=16, ny=16, nz=16)
+    _check_mmatrix(P.A)
+    assert P.partition == ("blocks", (8, 8, 8)) and P.tol == 1e-8

@@ -1,4 +1,4 @@
-"""The five synthetic workloads (and scaled-down variants for tests).
+"""The six synthetic workloads (and scaled-down variants for tests).
 
 Every workload is fully determined by its name and seed:
 
@@ -19,6 +19,13 @@ Every workload is fully determined by its name and seed:
         ``p = 0`` on x = 96.  1728 blocks of 8^3.  1000 seeded observation
         cells; observed pressures come from a forward solve with
         ``ln K + 0.1 g'`` (``g'`` an independent GRF, seed + 1).
+``c6``  64^3 periodic cross pattern (``cross_log_kappa``: kappa = 1e6 on three
+        orthogonal 2-cell-thick bars through the centre of every 8^3 tile, 1
+        elsewhere), ``p = 0`` on y = 0, ``p = 1`` on y = 64, no-flow elsewhere,
+        ``f = 0``.  512 blocks of 8^3.  tol 1e-8.
+
+``theta`` (c2, c6): the contrast sweep ``K -> K^theta`` (``ln K`` scaled by
+theta), so a field of contrast c gets contrast ``c^theta``.
 
 The seed defaults to the config number.  ``scale`` shrinks a config
 (dimensions divided, blocks kept) for fast tests.
@@ -28,11 +35,11 @@ from typing import Optional
 
 import numpy as np
 
-from .fields import grf, layered_log10k
+from .fields import cross_log_kappa, grf, layered_log10k
 from .grids import cartesian_faces, distorted_hex_faces
 from .tpfa import Faces, assemble, CSR
 
-CONFIG_NAMES = ("c1", "c2", "c3", "c4", "c5")
+CONFIG_NAMES = ("c1", "c2", "c3", "c4", "c5", "c6")
 
 
 @dataclass
@@ -79,9 +86,9 @@ def make_c1(seed=1, nx=64, ny=64, block=(16, 16, 1)):
     return cartesian_problem("c1", nx, ny, 1, g, [(0, 0, 0.0)], src, block, 1e-10)
 
 
-def make_c2(seed=2, nx=64, ny=64, nz=64, block=(8, 8, 8)):
+def make_c2(seed=2, nx=64, ny=64, nz=64, block=(8, 8, 8), theta=1.0):
     log10k = layered_log10k(nx, ny, nz, (16.0, 16.0, 2.0), 1.5, seed)
-    logK = log10k * np.log(10.0)
+    logK = theta * log10k * np.log(10.0)
     return cartesian_problem("c2", nx, ny, nz, logK, [(0, 0, 1.0), (0, 1, 0.0)],
                              None, block, 1e-8)
 
@@ -121,7 +128,14 @@ def make_c3(seed=3, nx=128, ny=128, nz=64, n_pairs=16, lo=200, hi=800):
                    tol=1e-8, extra=dict(wells=wells))
 
 
-_MAKERS = {"c1": make_c1, "c2": make_c2, "c3": make_c3, "c4": make_c4, "c5": make_c5}
+def make_c6(seed=6, nx=64, ny=64, nz=64, block=(8, 8, 8), theta=1.0):
+    logK = theta * cross_log_kappa(nx, ny, nz)
+    return cartesian_problem("c6", nx, ny, nz, logK, [(1, 0, 0.0), (1, 1, 1.0)],
+                             None, block, 1e-8)
+
+
+_MAKERS = {"c1": make_c1, "c2": make_c2, "c3": make_c3, "c4": make_c4, "c5": make_c5,
+           "c6": make_c6}
 
 
 def make_config(name, seed: Optional[int] = None, **kw):

@@ -12,6 +12,7 @@ cross pattern that is only in a figure):
 * ``layered_log10k``: one ``U[-3, 3]`` draw of log10 K per z-layer plus a GRF
   given in natural-log units, clipped to ``[-3, 3]`` (contrast exactly 1e6 when
   both clips are reached).
+* ``cross_log_kappa``: the periodic cross pattern (no randomness).
 
 Arrays are indexed ``[z, y, x]`` (C order), so the flat index of cell
 ``(i, j, k)`` is ``i + nx*(j + ny*k)``.
@@ -60,3 +61,21 @@ def layered_log10k(nx, ny, nz, ell_xyz, sigma, seed, lo=-3.0, hi=3.0):
     g = grf((nz, ny, nx), (ell_xyz[2], ell_xyz[1], ell_xyz[0]), sigma, seed)
     u = np.random.default_rng([seed, 1]).uniform(lo, hi, size=nz)
     return np.clip(u[:, None, None] + g / math.log(10.0), lo, hi)
+
+
+def cross_log_kappa(nx, ny, nz, base=8, lo=3, hi=4, kappa_hi=1.0e6):
+    """ln kappa of the periodic high-contrast cross pattern, shape ``[nz, ny, nx]``.
+
+    Reading of the cross-shaped field of the paper's scalability study (its
+    exact pattern is only drawn in a figure): the grid is tiled by
+    ``base^3`` tiles; inside a tile, a cell belongs to the cross when at least
+    two of its three tile coordinates lie in the central band ``[lo, hi]``,
+    i.e. three orthogonal bars through the tile centre.  Replicated over the
+    tiles, the bars join into straight channels along x, y and z that cross
+    the whole grid.  ``kappa = kappa_hi`` on the cross and 1 elsewhere.
+    """
+    def band(nn):
+        a = np.arange(nn) % base
+        return ((a >= lo) & (a <= hi)).astype(np.int64)
+    cnt = (band(nz)[:, None, None] + band(ny)[None, :, None] + band(nx)[None, None, :])
+    return np.where(cnt >= 2, math.log(kappa_hi), 0.0)
