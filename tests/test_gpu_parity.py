@@ -280,13 +280,20 @@ def test_pcg_16_rhs_bisect(prec):
     h.close()
 
 
-@pytest.mark.parametrize("name", ["c1", "layered"])
-def test_separate_interface_product_parity(name):
+@pytest.mark.parametrize("name,max_nrhs", [("c1", 1), ("layered", 1), ("ragged3d", 2),
+                                           ("bisect", 2), ("layered", 4)])
+def test_separate_interface_product_parity(name, max_nrhs):
     """The interface solve as its own launches (row-part outer products of
     the symmetric S^{-1}, then their sum in part order) instead of inside the
-    local kernel: apply within 1e-12 and PCG within 1e-8 of the oracle."""
+    local kernel, for 1, 2 and 4 right-hand-side layouts: apply within 1e-12
+    (also on two columns) and PCG within 1e-8 of the oracle."""
     A, part, m, b, ora = setup_case(name)
-    h = am.AlgMortar(A, part, m, separate_iface=True)
+    h = am.AlgMortar(A, part, m, separate_iface=True, max_nrhs=max_nrhs)
+    if max_nrhs >= 2:
+        R = np.random.default_rng(8).standard_normal((2, A.n))
+        Z = cpu(h.apply(gpu(R)))
+        for k in range(2):
+            assert rel(Z[k], ora.apply(R[k])) <= 1e-12
     r = np.random.default_rng(3).standard_normal(A.n)
     assert rel(cpu(h.apply(gpu(r))), ora.apply(r)) <= 1e-12
     As = A.to_scipy()
