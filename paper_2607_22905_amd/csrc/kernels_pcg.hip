@@ -252,7 +252,9 @@ __global__ __launch_bounds__(256) void k_update_xr(
     double* __restrict__ x, double* r, double* bpart, const double* __restrict__ pa, int npa,
     double* __restrict__ pb, PcgScalars* sc, PcgShared* sh, int init, int parity) {
   constexpr int KG = KGroup<NT>::v, TR = NT / KG;
-  constexpr int RPT = 4;
+  // two rows per thread cover a 512-cell subdomain in one pass with half the
+  // registers of four (more workgroups resident where there are many)
+  constexpr int RPT = 2;
   constexpr int QB = KG <= 2 ? 8 : 4;
   __shared__ double lds[4 * 32];
   const int s = blockIdx.x / TR, g = blockIdx.x % TR, k0 = g * KG;
