@@ -174,3 +174,41 @@ def test_smoother_errors():
         h.pcg_profile(gpu(P.b), 1e-10)
     assert e.value.status_name == "AM_ERR_UNSUPPORTED"
     h.close()
+
+
+def test_smoothed_pcg_several_rhs_and_replacement():
+    """Smoothed PCG on 3 right-hand sides solved together (each column against
+    its own oracle solve), after replacing a first smoother by another."""
+    P, part, m, blocks, nb, ora = setup("ragged3d")
+    h = am.AlgMortar(P.A, part, m, max_nrhs=4)
+    other, no = partition_blocks(P.dims, (6, 15, 4))
+    h.set_smoother(other, no, 1)
+    h.set_smoother(blocks, nb, 2)
+    rng = np.random.default_rng(9)
+    B = rng.standard_normal((3, P.n))
+    X, info, _ = h.pcg(gpu(B), 1e-10)
+    X = cpu(X)
+    so = SmoothedAlgMortarCPU(ora, blocks, 2)
+    As = ora.As
+    for k in range(3):
+        res = pcg(lambda v: As @ v, B[k], so.apply, 1e-10)
+        assert info[k]["converged"] == 1
+        assert abs(info[k]["iterations"] - res.iterations) <= 1
+        assert rel(X[k], res.x) <= 1e-8
+    h.close()
+
+
+def test_smoothed_cross_field_bf16_factors():
+    """Smoothing on the cross-shaped kappa = 1e6 field with BF16 factors
+    (flexible outer PCG): converges to the oracle's solution."""
+    P = make_config("c6", nx=32, ny=32, nz=32)
+    part, m = partition_blocks(P.dims, P.partition[1])
+    blocks, nb = partition_blocks(P.dims, (8, 8, 16))
+    h = am.AlgMortar(P.A, part, m, prec="bf16")
+    h.set_smoother(blocks, nb, 1)
+    x, info, _ = h.pcg(gpu(P.b), 1e-10)
+    assert info[0]["converged"] == 1 and info[0]["true_rel_res"] <= 2e-10
+    ora = AlgMortarCPU(P.A, part)
+    xo = pcg(lambda v: ora.As @ v, P.b, ora.apply, 1e-12).x
+    assert rel(cpu(x), xo) <= 1e-8
+    h.close()
