@@ -173,7 +173,8 @@ am_status algmortar_setup(const am_csr* A, const int32_t* part, int32_t nparts,
  * several subdomains; each block's bandwidth in ascending index order or RCM
  * order must be at most 128).  steps: nu in [0, 1000]; 0 removes the smoother.
  * The block factors take device memory like the subdomain factors.  Replaces
- * any earlier smoother; synchronizes `stream` and the handle.
+ * any earlier smoother; synchronizes the device (work on any stream may
+ * still use the earlier smoother), so `stream` needs no special handling.
  * algmortar_local_solve and algmortar_time_kernel are unaffected;
  * algmortar_pcg_profile returns AM_ERR_UNSUPPORTED while a smoother is set.
  * Errors: AM_ERR_ARG (partition), AM_ERR_UNSUPPORTED (bandwidth), AM_ERR_OOM;

@@ -615,8 +615,9 @@ am_status algmortar_set_smoother(am_handle h, const int32_t* blocks, int32_t nbl
   if (steps < 0 || steps > 1000) return fail(h, AM_ERR_ARG, "steps must be in [0, 1000]");
   DeviceState& d = h->d;
   HCHK(hipSetDevice(d.device));
-  if (stream) HCHK(hipStreamSynchronize((hipStream_t)stream));
-  HCHK(hipStreamSynchronize(h->own));
+  // applies on any stream may still read the old smoother's buffers
+  HCHK(hipDeviceSynchronize());
+  (void)stream;
   drop_smoother(h);
   if (steps == 0) return AM_OK;
   if (!blocks) return fail(h, AM_ERR_ARG, "null block partition");

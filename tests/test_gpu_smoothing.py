@@ -200,14 +200,16 @@ def test_smoothed_pcg_several_rhs_and_replacement():
 
 def test_smoothed_cross_field_bf16_factors():
     """Smoothing on the cross-shaped kappa = 1e6 field with BF16 factors
-    (flexible outer PCG): converges to the oracle's solution."""
+    (flexible outer PCG): converges to the oracle's solution.  The field's
+    contrast makes A ill conditioned (a 1e-10 residual leaves errors near
+    3e-8), so both sides solve to 1e-12."""
     P = make_config("c6", nx=32, ny=32, nz=32)
     part, m = partition_blocks(P.dims, P.partition[1])
     blocks, nb = partition_blocks(P.dims, (8, 8, 16))
     h = am.AlgMortar(P.A, part, m, prec="bf16")
     h.set_smoother(blocks, nb, 1)
-    x, info, _ = h.pcg(gpu(P.b), 1e-10)
-    assert info[0]["converged"] == 1 and info[0]["true_rel_res"] <= 2e-10
+    x, info, _ = h.pcg(gpu(P.b), 1e-12)
+    assert info[0]["converged"] == 1 and info[0]["true_rel_res"] <= 2e-12
     ora = AlgMortarCPU(P.A, part)
     xo = pcg(lambda v: ora.As @ v, P.b, ora.apply, 1e-12).x
     assert rel(cpu(x), xo) <= 1e-8
