@@ -455,7 +455,7 @@ static am_status setup_impl(const am_csr* A, const int32_t* part, int32_t nparts
   if (!d.fuse_eta && NL > 0) {
     // enough (row block, part) waves to fill the chip, each part >= 64 rows
     const int64_t nrb = (NL + 63) / 64;
-    d.op_parts = (int32_t)std::max<int64_t>(1, std::min<int64_t>({64, (4096 + nrb - 1) / nrb, NL / 64}));
+    d.op_parts = (int32_t)std::max<int64_t>(1, std::min<int64_t>({64, (8192 + nrb - 1) / nrb, NL / 64}));
     SCHK(dalloc(al, &d.ypart, (size_t)d.op_parts * d.ldS * d.max_nrhs));
   }
 

@@ -294,6 +294,66 @@ __global__ __launch_bounds__(256) void k_iface_op(int NL, int ldS, const double*
   for (int k = 0; k < NR; ++k) ypart[((size_t)p * ldS + r) * NR + k] = acc[k];
 }
 
+// The same product for 4 to 16 right-hand sides on the FP64 matrix cores:
+// wave (rb, p) accumulates the 64 x NR block ypart[p][64 rb ..][.] as four
+// 16 x 16 tiles, D += A B with A = S^{-1}[m0 .. m0+3][16 rows] (symmetric,
+// so the rows m of S^{-1} stand for its columns) and B = b[m0 .. m0+3][NR
+// columns, zero-padded to 16].  v_mfma_f64_16x16x4_f64 lane l holds
+// A[l % 16][l / 16], B[l / 16][l % 16] and D[l / 16 + 4 v][l % 16], v < 4.
+// S^{-1} is read once (four coalesced 128-byte rows per load); the FMAs run
+// on the matrix cores, so 16 right-hand sides cost no more issue slots than 4.
+typedef double am_d4 __attribute__((ext_vector_type(4)));
+
+template <int NR>
+__global__ __launch_bounds__(256) void k_iface_op_mfma(int NL, int ldS, const double* __restrict__ Sinv,
+                                                       const double* __restrict__ bpart,
+                                                       double* __restrict__ ypart, int P, int pcg,
+                                                       int init, const PcgShared* sh) {
+  static_assert(NR >= 1 && NR <= 16, "one 16-column tile");
+  if (pcg && !init && all_done(sh)) return;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  const int nrb = (NL + 63) / 64;
+  if (wv >= nrb * P) return;
+  const int rb = wv % nrb, p = wv / nrb;
+  const int per = (NL + P - 1) / P;
+  const int mb = p * per, me = min(NL, mb + per);
+  const int li = lane % 16, lk = lane / 16;
+  const double* col = Sinv + 64 * rb + li;  // column 64 rb + 16 sub + li of row m
+  am_d4 acc[4];
+#pragma unroll
+  for (int sub = 0; sub < 4; ++sub) acc[sub] = am_d4{0.0, 0.0, 0.0, 0.0};
+  // U chunks of 4 rows per step, every load of the step issued before its
+  // products, so that a wave keeps 4 U coalesced row loads in flight
+  constexpr int U = 4;
+  for (int m0 = mb; m0 < me; m0 += 4 * U) {
+    double av[U][4], bv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int m = m0 + 4 * u + lk;
+      const bool ok = m < me;
+      bv[u] = (ok && li < NR)
+                  ? bpart[(size_t)(2 * m) * NR + li] + bpart[(size_t)(2 * m + 1) * NR + li]
+                  : 0.0;
+#pragma unroll
+      for (int sub = 0; sub < 4; ++sub) av[u][sub] = ok ? col[(size_t)m * ldS + 16 * sub] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int sub = 0; sub < 4; ++sub)
+        acc[sub] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][sub], bv[u], acc[sub], 0, 0, 0);
+  }
+  if (li < NR)
+#pragma unroll
+    for (int sub = 0; sub < 4; ++sub)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 64 * rb + 16 * sub + lk + 4 * v;
+        ypart[((size_t)p * ldS + r) * NR + li] = acc[sub][v];
+      }
+}
+
 // eta[r][k] = sum_p ypart[p][r][k] in part order.  In PCG mode workgroup 0
 // first folds the ||r||^2 partials of the update launch and applies the stop
 // test ||r|| <= tol ||b|| (the next launches read its outcome).
@@ -383,8 +443,12 @@ template <int NR>
 static void gemv_t(DeviceState& d, hipStream_t st, int pcg, int init) {
   const int nrb = (int)((d.NL + 63) / 64);
   const unsigned nw = (unsigned)std::max(1, nrb * d.op_parts);
-  hipLaunchKernelGGL((k_iface_op<NR>), dim3((nw + 3) / 4), dim3(256), 0, st, (int)d.NL, d.ldS,
-                     d.Sinv, d.bpart, d.ypart, d.op_parts, pcg, init, d.shared);
+  if constexpr (NR >= 4)
+    hipLaunchKernelGGL((k_iface_op_mfma<NR>), dim3((nw + 3) / 4), dim3(256), 0, st, (int)d.NL,
+                       d.ldS, d.Sinv, d.bpart, d.ypart, d.op_parts, pcg, init, d.shared);
+  else
+    hipLaunchKernelGGL((k_iface_op<NR>), dim3((nw + 3) / 4), dim3(256), 0, st, (int)d.NL, d.ldS,
+                       d.Sinv, d.bpart, d.ypart, d.op_parts, pcg, init, d.shared);
   const unsigned nb = (unsigned)std::max<int64_t>(1, (d.NL * NR + 255) / 256);
   hipLaunchKernelGGL((k_iface_reduce<NR>), dim3(nb), dim3(256), 0, st, (int)d.NL, d.ldS, d.ypart,
                      d.op_parts, d.eta, pcg, init, d.red.pb, d.m, d.sc, d.shared);
