@@ -915,6 +915,276 @@ __global__ __launch_bounds__(64 * G * W) void k_localt(
     }
 }
 
+// Tile form for 16 right-hand sides on the FP64 matrix cores (FP64 factors,
+// window 64, interface solve done before the launch).  Each tile pass is a
+// dense 64 x 64 by 64 x 16 product, so the four waves of the workgroup each
+// take 16 rows of the output block and accumulate all 16 right-hand sides
+// with v_mfma_f64_16x16x4_f64 over the 64 columns: no partial sums cross
+// waves.  Lane l holds A[l % 16][l / 16], B[l / 16][l % 16] and
+// D[l / 16 + 4 v][l % 16] (v < 4).  The block vectors (64 rows x 16) live in
+// LDS (two buffers, pitch 17); the tiles are staged as in k_localt.
+//   forward  y_b = t_b + Nlow_b t_b,   out_b = dinv y_b,
+//            t_{b+1} = r_{b+1} - U_b y_b
+//   backward s_b = out_b - U_b^T x_{b+1},   x_b = s_b + Nlow_b^T s_b,
+//            z_b = x_b + sum_q phat_q eta_q   (mode >= 1), PCG dots (mode 2)
+// with Nlow_b the strictly lower part of tile b (the inverted diagonal
+// block) and U_b its upper part with the diagonal (the coupling to block
+// b + 1).
+typedef double am_mf_d4 __attribute__((ext_vector_type(4)));
+constexpr int kMfVP = 17;  // LDS pitch of a block-vector row (16 values + 1)
+
+
+// acc += sum over the 64 columns of A[rows][col] B[col][.] for a 16-row strip:
+// the 16 operand pairs are read from LDS first, then four independent chains
+// of four products (columns 4 kk + lk with kk = c mod 4 in chain c) are
+// added in chain order.
+template <typename AF, typename BF>
+__device__ __forceinline__ am_mf_d4 mf_pass(am_mf_d4 acc, AF&& afn, BF&& bfn) {
+  double a[16], b[16];
+#pragma unroll
+  for (int kk = 0; kk < 16; ++kk) {
+    a[kk] = afn(kk);
+    b[kk] = bfn(kk);
+  }
+  am_mf_d4 c[4];
+  c[0] = acc;
+#pragma unroll
+  for (int t = 1; t < 4; ++t) c[t] = am_mf_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kk = 0; kk < 16; ++kk)
+    c[kk % 4] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk], b[kk], c[kk % 4], 0, 0, 0);
+  return (c[0] + c[1]) + (c[2] + c[3]);
+}
+
+template <int NT>
+__global__ __launch_bounds__(256) void k_localt_mf(
+    const int32_t* __restrict__ subs, const int64_t* __restrict__ sub_ptr,
+    const int64_t* __restrict__ roff, const int64_t* __restrict__ fac_off,
+    const double* __restrict__ Lc, const double* __restrict__ dinv, const double* rin,
+    double* out, int mode, const int64_t* __restrict__ isub_ptr,
+    const int32_t* __restrict__ isub_list, const int64_t* __restrict__ mbf_off,
+    const double* __restrict__ mbf, const double* __restrict__ eta, const double* __restrict__ qv,
+    double* __restrict__ partial, unsigned blk_off, PcgShared* sh, int64_t nrows) {
+  static_assert(NT == 16, "one 16-column matrix-core tile");
+  constexpr int PITCH = 65;
+  constexpr int CH = 64 * PITCH;
+  constexpr int NTHR = 256;
+  constexpr int NLD = 64 * 64 / (2 * NTHR);  // 16-byte loads per thread per tile
+  constexpr int PD = 2;
+  __shared__ double tile[2][CH];
+  __shared__ double vb[2][64 * kMfVP];
+  __shared__ double eta_s[64 * NT];
+  __shared__ double dots[4][2 * NT];
+
+  const int s = subs[blockIdx.x];
+  const int64_t base = sub_ptr[s];
+  const int N = (int)(sub_ptr[s + 1] - base);
+  const int64_t ro = roff[s];
+  const int NP = (int)(roff[s + 1] - ro);
+  const int NB = NP / 64;
+  const double* lc = Lc + fac_off[s];
+  const double* dv = dinv + ro;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int li = lane % 16, lk = lane / 16;
+  const int64_t i0 = isub_ptr[s];
+  const int ns = mode >= 1 ? (int)(isub_ptr[s + 1] - i0) : 0;
+  const double* P = mbf + mbf_off[s];
+  auto vi = [&](int row, int k) { return vix<NT>(nrows, base + row, k); };
+
+  uint4 pre[PD][NLD];
+  auto tile_load = [&](int b, int slot) {
+    const uint4* src = reinterpret_cast<const uint4*>(lc + (size_t)64 * b * 64);
+#pragma unroll
+    for (int u = 0; u < NLD; ++u) pre[slot][u] = src[u * NTHR + threadIdx.x];
+  };
+  auto tile_store = [&](int buf, int slot) {
+#pragma unroll
+    for (int u = 0; u < NLD; ++u) {
+      const int e0 = (u * NTHR + (int)threadIdx.x) * 2;  // column e0 / 64, rows e0 % 64 ..
+      double* dst = tile[buf] + (e0 / 64) * PITCH + (e0 % 64);
+      double v[2];
+      __builtin_memcpy(v, &pre[slot][u], 16);
+      dst[0] = v[0];
+      dst[1] = v[1];
+    }
+  };
+  // rows of this lane's part of the D layout: 16 w + lk + 4 v
+  auto drow = [&](int v) { return 16 * w + lk + 4 * v; };
+
+  tile_load(0, 0);
+  if (mode == 2 && all_done(sh)) return;
+  for (int t = threadIdx.x; t < ns * NT; t += NTHR)
+    eta_s[t] = eta[(size_t)isub_list[i0 + t / NT] * NT + (t % NT)];
+  tile_store(0, 0);
+  if (1 < NB) tile_load(1, 1);
+  if (2 < NB) tile_load(2, 0);
+  // t_0 = r of block 0
+  for (int e = threadIdx.x; e < 64 * NT; e += NTHR) {
+    const int row = e / NT, k = e % NT;
+    vb[0][row * kMfVP + k] = row < N ? rin[vi(row, k)] : 0.0;
+  }
+  __syncthreads();
+
+  // ---- forward sweep ----
+  auto fwd_body = [&](const int b, auto parc) {
+    constexpr int par = decltype(parc)::v;  // b & 1
+    const int j0 = 64 * b;
+    double rn[4], dvl[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = j0 + 64 + drow(v);
+      rn[v] = row < N ? rin[vi(row, li)] : 0.0;
+      dvl[v] = dv[j0 + drow(v)];
+    }
+    const double* T = tile[par];
+    // pass B: y = t + Nlow t
+    am_mf_d4 acc;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] = vb[0][drow(v) * kMfVP + li];
+    {
+      const int ii = 16 * w + li;
+      acc = mf_pass(
+          acc, [&](int kk) { const int jj = 4 * kk + lk; return ii > jj ? T[jj * PITCH + ii] : 0.0; },
+          [&](int kk) { return vb[0][(4 * kk + lk) * kMfVP + li]; });
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      vb[1][drow(v) * kMfVP + li] = acc[v];
+      const int row = j0 + drow(v);
+      if (row < N) out[vi(row, li)] = acc[v] * dvl[v];
+    }
+    if (b + 1 < NB) {
+      tile_store(1 - par, (par + 1) % PD);
+      if (b + 1 + PD < NB) tile_load(b + 1 + PD, (par + 1) % PD);
+    }
+    __syncthreads();
+    // pass A: t_{b+1} = r_{b+1} - U y
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] = rn[v];
+    {
+      const int ii = 16 * w + li;
+      acc = mf_pass(
+          acc, [&](int kk) { const int jj = 4 * kk + lk; return ii <= jj ? -T[jj * PITCH + ii] : 0.0; },
+          [&](int kk) { return vb[1][(4 * kk + lk) * kMfVP + li]; });
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) vb[0][drow(v) * kMfVP + li] = acc[v];
+    __syncthreads();
+  };
+  for (int b = 0; b < NB; b += 2) {
+    fwd_body(b, IC<0>{});
+    if (b + 1 < NB) fwd_body(b + 1, IC<1>{});
+  }
+
+  // ---- backward sweep: tiles NB-1 and NB-2 are still in LDS ----
+  if (NB > 2) {
+    if ((NB - 3) & 1)
+      tile_load(NB - 3, 1);
+    else
+      tile_load(NB - 3, 0);
+  }
+  // x_{NB} = 0
+  for (int e = threadIdx.x; e < 64 * NT; e += NTHR) vb[1][(e / NT) * kMfVP + e % NT] = 0.0;
+  __syncthreads();
+  double rz = 0.0, qz = 0.0;  // column li of this lane's rows
+  auto bwd_body = [&](const int b, auto parc) {
+    constexpr int par = decltype(parc)::v;  // b & 1
+    const int j0 = 64 * b;
+    const double* T = tile[par];
+    double vv[4], rp[4], qp[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = j0 + drow(v);
+      const bool ok = row < N;
+      vv[v] = ok ? out[vi(row, li)] : 0.0;
+      rp[v] = (ok && mode == 2) ? rin[vi(row, li)] : 0.0;
+      qp[v] = (ok && mode == 2) ? qv[vi(row, li)] : 0.0;
+    }
+    // basis-function values of this block for the reconstruction, fetched
+    // before the passes: A[row 16 w + li][slot q0 + lk] of z += phat eta
+    double pa[16];
+    {
+      const int ra = j0 + 16 * w + li;
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        const int q = 4 * c + lk;
+        pa[c] = (q < ns && ra < N) ? P[(size_t)q * N + ra] : 0.0;
+      }
+    }
+    // pass A: s = out_b - U^T x_{b+1}
+    am_mf_d4 acc;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] = vv[v];
+    {
+      const int ii = 16 * w + li;  // output row ii, tile row jj
+      acc = mf_pass(
+          acc, [&](int kk) { const int jj = 4 * kk + lk; return jj <= ii ? -T[ii * PITCH + jj] : 0.0; },
+          [&](int kk) { return vb[1][(4 * kk + lk) * kMfVP + li]; });
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) vb[0][drow(v) * kMfVP + li] = acc[v];
+    __syncthreads();
+    // pass B: x = s + Nlow^T s
+    {
+      const int ii = 16 * w + li;
+      acc = mf_pass(
+          acc, [&](int kk) { const int jj = 4 * kk + lk; return jj > ii ? T[ii * PITCH + jj] : 0.0; },
+          [&](int kk) { return vb[0][(4 * kk + lk) * kMfVP + li]; });
+    }
+    if (b > 0) {
+      if (b < NB - 1) tile_store(1 - par, (par + 1) % PD);
+      if (b - 1 - PD >= 0) tile_load(b - 1 - PD, (par + 1) % PD);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) vb[1][drow(v) * kMfVP + li] = acc[v];
+    // z = x + P_b eta on the matrix cores (slots in chunks of 4)
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      if (4 * c >= ns) break;  // uniform
+      const int q = 4 * c + lk;
+      const double e = q < ns ? eta_s[q * NT + li] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[c], e, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = j0 + drow(v);
+      if (row < N) {
+        out[vi(row, li)] = acc[v];
+        rz = fma(rp[v], acc[v], rz);
+        qz = fma(qp[v], acc[v], qz);
+      }
+    }
+    __syncthreads();
+  };
+  {
+    int b = NB - 1;
+    if (b & 1) bwd_body(b--, IC<1>{});
+    for (; b >= 0; b -= 2) {
+      bwd_body(b, IC<0>{});
+      if (b - 1 >= 0) bwd_body(b - 1, IC<1>{});
+    }
+  }
+
+  if (mode != 2) return;
+  // lanes l, l ^ 16, l ^ 32, l ^ 48 hold the same column
+  rz += __shfl_xor(rz, 16, 64);
+  rz += __shfl_xor(rz, 32, 64);
+  qz += __shfl_xor(qz, 16, 64);
+  qz += __shfl_xor(qz, 32, 64);
+  if (lane < 16) {
+    dots[w][lane] = rz;
+    dots[w][NT + lane] = qz;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * NT) {
+    double a = 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a += dots[u][threadIdx.x];
+    partial[(size_t)(blk_off + blockIdx.x) * 2 * NT + threadIdx.x] = a;
+  }
+}
+
 // MBFs: one wave per (subdomain, slot): rhs = -B_s psi_n scattered from the
 // boundary weights, then the two sweeps in place.
 template <typename FT, int C>
@@ -1080,7 +1350,17 @@ hipError_t localt_shape(DeviceState& d, const double* r, double* z, const double
     };
     if (bk == 0) {
       using S = TileAt<FT, 1, NT, I>;
-      go(k_localt<FT, 1, NT, S::G, S::W>, 64 * S::G * S::W);
+      bool mf = false;
+      if constexpr (NT == 16 && sizeof(FT) == 8) {
+        if (!d.fuse_eta) {
+          mf = true;
+          hipLaunchKernelGGL(k_localt_mf<16>, dim3(nb), dim3(256), 0, st, d.d_bucket_sub[bk], d.sub_ptr,
+                             d.roff, d.fac_off, (const double*)d.Lc, (const double*)d.invd, r, z,
+                             mode, d.isub_ptr, d.isub_list, d.mbf_off, d.mbf, eta, d.q, d.red.pd,
+                             off, d.shared, d.n);
+        }
+      }
+      if (!mf) go(k_localt<FT, 1, NT, S::G, S::W>, 64 * S::G * S::W);
     } else {
       using S = TileAt<FT, 2, NT, I>;
       go(k_localt<FT, 2, NT, S::G, S::W>, 64 * S::G * S::W);

@@ -328,6 +328,15 @@ def test_separate_interface_product_parity(name, max_nrhs):
         Z = cpu(h.apply(gpu(R)))
         for k in range(ncol):
             assert rel(Z[k], ora.apply(R[k])) <= 1e-12
+        if max_nrhs == 16:  # the matrix-core local kernel inside PCG
+            X, infos, _ = h.pcg(gpu(R), 1e-10)
+            X = cpu(X)
+            As = A.to_scipy()
+            for k in range(ncol):
+                refk = pcg(lambda v: As @ v, R[k], ora.apply, 1e-10)
+                assert infos[k]["converged"] == 1
+                assert abs(infos[k]["iterations"] - refk.iterations) <= 1
+                assert rel(X[k], refk.x) <= 1e-8
     r = np.random.default_rng(3).standard_normal(A.n)
     assert rel(cpu(h.apply(gpu(r))), ora.apply(r)) <= 1e-12
     As = A.to_scipy()
