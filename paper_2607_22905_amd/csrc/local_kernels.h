@@ -940,19 +940,22 @@ constexpr int kMfVP = 17;  // LDS pitch of a block-vector row (16 values + 1)
 // added in chain order.
 template <typename AF, typename BF>
 __device__ __forceinline__ am_mf_d4 mf_pass(am_mf_d4 acc, AF&& afn, BF&& bfn) {
-  double a[16], b[16];
-#pragma unroll
-  for (int kk = 0; kk < 16; ++kk) {
-    a[kk] = afn(kk);
-    b[kk] = bfn(kk);
-  }
   am_mf_d4 c[4];
   c[0] = acc;
 #pragma unroll
   for (int t = 1; t < 4; ++t) c[t] = am_mf_d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int kk = 0; kk < 16; ++kk)
-    c[kk % 4] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk], b[kk], c[kk % 4], 0, 0, 0);
+  for (int h = 0; h < 2; ++h) {  // two halves of 8 operand pairs (registers)
+    double a[8], b[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      a[u] = afn(8 * h + u);
+      b[u] = bfn(8 * h + u);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      c[u % 4] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], c[u % 4], 0, 0, 0);
+  }
   return (c[0] + c[1]) + (c[2] + c[3]);
 }
 
@@ -970,8 +973,8 @@ __global__ __launch_bounds__(256) void k_localt_mf(
   constexpr int CH = 64 * PITCH;
   constexpr int NTHR = 256;
   constexpr int NLD = 64 * 64 / (2 * NTHR);  // 16-byte loads per thread per tile
-  constexpr int PD = 2;
-  __shared__ double tile[2][CH];
+  constexpr int PD = 1;  // one tile ahead in registers (two workgroups per CU)
+  __shared__ double tile[CH];  // one buffer: two workgroups fit a CU
   __shared__ double vb[2][64 * kMfVP];
   __shared__ double eta_s[64 * NT];
   __shared__ double dots[4][2 * NT];
@@ -998,11 +1001,11 @@ __global__ __launch_bounds__(256) void k_localt_mf(
 #pragma unroll
     for (int u = 0; u < NLD; ++u) pre[slot][u] = src[u * NTHR + threadIdx.x];
   };
-  auto tile_store = [&](int buf, int slot) {
+  auto tile_store = [&](int slot) {
 #pragma unroll
     for (int u = 0; u < NLD; ++u) {
       const int e0 = (u * NTHR + (int)threadIdx.x) * 2;  // column e0 / 64, rows e0 % 64 ..
-      double* dst = tile[buf] + (e0 / 64) * PITCH + (e0 % 64);
+      double* dst = tile + (e0 / 64) * PITCH + (e0 % 64);
       double v[2];
       __builtin_memcpy(v, &pre[slot][u], 16);
       dst[0] = v[0];
@@ -1016,9 +1019,8 @@ __global__ __launch_bounds__(256) void k_localt_mf(
   if (mode == 2 && all_done(sh)) return;
   for (int t = threadIdx.x; t < ns * NT; t += NTHR)
     eta_s[t] = eta[(size_t)isub_list[i0 + t / NT] * NT + (t % NT)];
-  tile_store(0, 0);
-  if (1 < NB) tile_load(1, 1);
-  if (2 < NB) tile_load(2, 0);
+  tile_store(0);
+  if (1 < NB) tile_load(1, 0);
   // t_0 = r of block 0
   for (int e = threadIdx.x; e < 64 * NT; e += NTHR) {
     const int row = e / NT, k = e % NT;
@@ -1037,7 +1039,7 @@ __global__ __launch_bounds__(256) void k_localt_mf(
       rn[v] = row < N ? rin[vi(row, li)] : 0.0;
       dvl[v] = dv[j0 + drow(v)];
     }
-    const double* T = tile[par];
+    const double* T = tile;
     // pass B: y = t + Nlow t
     am_mf_d4 acc;
 #pragma unroll
@@ -1054,10 +1056,6 @@ __global__ __launch_bounds__(256) void k_localt_mf(
       const int row = j0 + drow(v);
       if (row < N) out[vi(row, li)] = acc[v] * dvl[v];
     }
-    if (b + 1 < NB) {
-      tile_store(1 - par, (par + 1) % PD);
-      if (b + 1 + PD < NB) tile_load(b + 1 + PD, (par + 1) % PD);
-    }
     __syncthreads();
     // pass A: t_{b+1} = r_{b+1} - U y
 #pragma unroll
@@ -1070,20 +1068,20 @@ __global__ __launch_bounds__(256) void k_localt_mf(
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) vb[0][drow(v) * kMfVP + li] = acc[v];
-    __syncthreads();
+    __syncthreads();  // every wave is done with tile b
+    if (b + 1 < NB) {
+      tile_store((par + 1) % PD);
+      if (b + 1 + PD < NB) tile_load(b + 1 + PD, (par + 1) % PD);
+      __syncthreads();
+    }
   };
   for (int b = 0; b < NB; b += 2) {
     fwd_body(b, IC<0>{});
     if (b + 1 < NB) fwd_body(b + 1, IC<1>{});
   }
 
-  // ---- backward sweep: tiles NB-1 and NB-2 are still in LDS ----
-  if (NB > 2) {
-    if ((NB - 3) & 1)
-      tile_load(NB - 3, 1);
-    else
-      tile_load(NB - 3, 0);
-  }
+  // ---- backward sweep: tile NB-1 is still in LDS ----
+  if (NB > 1) tile_load(NB - 2, 0);
   // x_{NB} = 0
   for (int e = threadIdx.x; e < 64 * NT; e += NTHR) vb[1][(e / NT) * kMfVP + e % NT] = 0.0;
   __syncthreads();
@@ -1091,7 +1089,7 @@ __global__ __launch_bounds__(256) void k_localt_mf(
   auto bwd_body = [&](const int b, auto parc) {
     constexpr int par = decltype(parc)::v;  // b & 1
     const int j0 = 64 * b;
-    const double* T = tile[par];
+    const double* T = tile;
     double vv[4], rp[4], qp[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -1103,14 +1101,13 @@ __global__ __launch_bounds__(256) void k_localt_mf(
     }
     // basis-function values of this block for the reconstruction, fetched
     // before the passes: A[row 16 w + li][slot q0 + lk] of z += phat eta
-    double pa[16];
-    {
-      const int ra = j0 + 16 * w + li;
+    constexpr int NPA = 8;  // slots 0..31 fetched ahead, the rest when used
+    const int ra = j0 + 16 * w + li;
+    double pa[NPA];
 #pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        const int q = 4 * c + lk;
-        pa[c] = (q < ns && ra < N) ? P[(size_t)q * N + ra] : 0.0;
-      }
+    for (int c = 0; c < NPA; ++c) {
+      const int q = 4 * c + lk;
+      pa[c] = (q < ns && ra < N) ? P[(size_t)q * N + ra] : 0.0;
     }
     // pass A: s = out_b - U^T x_{b+1}
     am_mf_d4 acc;
@@ -1132,19 +1129,21 @@ __global__ __launch_bounds__(256) void k_localt_mf(
           acc, [&](int kk) { const int jj = 4 * kk + lk; return jj > ii ? T[ii * PITCH + jj] : 0.0; },
           [&](int kk) { return vb[0][(4 * kk + lk) * kMfVP + li]; });
     }
-    if (b > 0) {
-      if (b < NB - 1) tile_store(1 - par, (par + 1) % PD);
-      if (b - 1 - PD >= 0) tile_load(b - 1 - PD, (par + 1) % PD);
-    }
 #pragma unroll
     for (int v = 0; v < 4; ++v) vb[1][drow(v) * kMfVP + li] = acc[v];
     // z = x + P_b eta on the matrix cores (slots in chunks of 4)
 #pragma unroll
-    for (int c = 0; c < 16; ++c) {
+    for (int c = 0; c < NPA; ++c) {
       if (4 * c >= ns) break;  // uniform
       const int q = 4 * c + lk;
       const double e = q < ns ? eta_s[q * NT + li] : 0.0;
       acc = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[c], e, acc, 0, 0, 0);
+    }
+    for (int c = NPA; 4 * c < ns; ++c) {
+      const int q = 4 * c + lk;
+      const double av = (q < ns && ra < N) ? P[(size_t)q * N + ra] : 0.0;
+      const double e = q < ns ? eta_s[q * NT + li] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, e, acc, 0, 0, 0);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -1155,7 +1154,12 @@ __global__ __launch_bounds__(256) void k_localt_mf(
         qz = fma(qp[v], acc[v], qz);
       }
     }
-    __syncthreads();
+    __syncthreads();  // every wave is done with tile b
+    if (b > 0) {
+      tile_store((par + 1) % PD);  // tile b - 1
+      if (b - 1 - PD >= 0) tile_load(b - 1 - PD, (par + 1) % PD);
+      __syncthreads();
+    }
   };
   {
     int b = NB - 1;
