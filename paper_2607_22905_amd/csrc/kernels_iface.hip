@@ -79,28 +79,68 @@ __device__ __forceinline__ void load_tile(Tile& T, const double* p, int ld, bool
   }
 }
 
-// acc += A * B for the thread's 4 x 4 block (rows 4*ty.., cols 4*tx..)
-__device__ __forceinline__ void tile_mac(double (&acc)[4][4], const Tile& A, const Tile& B) {
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-#pragma unroll 4
-  for (int k = 0; k < 64; ++k) {
-    double a[4], b[4];
+// A tile through registers, for 256-thread workgroups: tile_fetch issues all
+// 16 loads of the thread before any is used (one memory round trip per tile
+// instead of one per row of threads), tile_put stores them to LDS.
+struct TileRegs {
+  double v[16];
+};
+
+__device__ __forceinline__ void tile_fetch(TileRegs& R, const double* p, int ld) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] = A[4 * ty + i][k];
-#pragma unroll
-    for (int jj = 0; jj < 4; ++jj) b[jj] = B[k][4 * tx + jj];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int jj = 0; jj < 4; ++jj) acc[i][jj] = fma(a[i], b[jj], acc[i][jj]);
+  for (int u = 0; u < 16; ++u) {
+    const int r = (threadIdx.x >> 6) + 4 * u, c = threadIdx.x & 63;
+    R.v[u] = p[(size_t)r * ld + c];
   }
 }
 
-__device__ __forceinline__ void zero_acc(double (&acc)[4][4]) {
+__device__ __forceinline__ void tile_put(Tile& T, const TileRegs& R, bool trans) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int u = 0; u < 16; ++u) {
+    const int r = (threadIdx.x >> 6) + 4 * u, c = threadIdx.x & 63;
+    if (trans)
+      T[c][r] = R.v[u];
+    else
+      T[r][c] = R.v[u];
+  }
+}
+
+// acc += A * B for two 64 x 64 tiles on the FP64 matrix cores: wave w owns
+// rows 16 w .. 16 w + 15 and keeps four 16 x 16 accumulators (columns 16 t ..);
+// v_mfma_f64_16x16x4_f64 lane l holds A[l % 16][l / 16], B[l / 16][l % 16]
+// and D[l / 16 + 4 v][l % 16], v < 4.
+typedef double am_d4 __attribute__((ext_vector_type(4)));
+struct MfAcc {
+  am_d4 t[4];
+};
+
+__device__ __forceinline__ void mf_zero(MfAcc& acc) {
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj) acc[i][jj] = 0.0;
+  for (int t = 0; t < 4; ++t) acc.t[t] = am_d4{0.0, 0.0, 0.0, 0.0};
+}
+
+// 256 threads = 4 waves
+__device__ __forceinline__ void mf_mac(MfAcc& acc, const Tile& A, const Tile& B) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane % 16, lk = lane / 16;
+#pragma unroll 4
+  for (int ks = 0; ks < 16; ++ks) {
+    const double a = A[16 * w + li][4 * ks + lk];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      acc.t[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, B[4 * ks + lk][16 * t + li], acc.t[t], 0, 0, 0);
+  }
+}
+
+// calls f(row, col, value) for the thread's 16 entries of the tile
+template <typename F>
+__device__ __forceinline__ void mf_each(const MfAcc& acc, F&& f) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane % 16, lk = lane / 16;
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) f(16 * w + lk + 4 * v, 16 * t + li, acc.t[t][v]);
 }
 
 // Cholesky of the diagonal tile (b, b), in place (lower; upper zeroed).
@@ -162,18 +202,17 @@ __global__ __launch_bounds__(256) void k_syrk_update(double* A, int ld, int b) {
   if (j > i) return;
   __shared__ Tile Ai;
   __shared__ Tile Bj;
-  load_tile(Ai, A + (size_t)i * 64 * ld + (size_t)b * 64, ld, false);
-  load_tile(Bj, A + (size_t)j * 64 * ld + (size_t)b * 64, ld, true);
+  TileRegs ra, rb;
+  tile_fetch(ra, A + (size_t)i * 64 * ld + (size_t)b * 64, ld);
+  tile_fetch(rb, A + (size_t)j * 64 * ld + (size_t)b * 64, ld);
+  tile_put(Ai, ra, false);
+  tile_put(Bj, rb, true);
   __syncthreads();
-  double acc[4][4];
-  zero_acc(acc);
-  tile_mac(acc, Ai, Bj);
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  MfAcc acc;
+  mf_zero(acc);
+  mf_mac(acc, Ai, Bj);
   double* pc = A + (size_t)i * 64 * ld + (size_t)j * 64;
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) pc[(size_t)(4 * ty + r) * ld + 4 * tx + c] -= acc[r][c];
+  mf_each(acc, [&](int r, int c, double v) { pc[(size_t)r * ld + c] -= v; });
 }
 
 // Inverse of each diagonal tile of L (lower), one column per thread.
@@ -206,29 +245,32 @@ __global__ __launch_bounds__(256) void k_trtri_off(const double* L, double* Li, 
   const int i = d + blockIdx.x, j = blockIdx.x;
   __shared__ Tile As;
   __shared__ Tile Bs;
-  double acc[4][4];
-  zero_acc(acc);
+  MfAcc acc;
+  mf_zero(acc);
+  // the tiles of step k + 1 are in flight while step k runs on the matrix cores
+  TileRegs ra, rb;
+  tile_fetch(ra, L + (size_t)i * 64 * ld + (size_t)j * 64, ld);
+  tile_fetch(rb, Li + (size_t)j * 64 * ld + (size_t)j * 64, ld);
   for (int k = j; k < i; ++k) {
-    load_tile(As, L + (size_t)i * 64 * ld + (size_t)k * 64, ld, false);
-    load_tile(Bs, Li + (size_t)k * 64 * ld + (size_t)j * 64, ld, false);
+    tile_put(As, ra, false);
+    tile_put(Bs, rb, false);
     __syncthreads();
-    tile_mac(acc, As, Bs);
+    if (k + 1 < i) {
+      tile_fetch(ra, L + (size_t)i * 64 * ld + (size_t)(k + 1) * 64, ld);
+      tile_fetch(rb, Li + (size_t)(k + 1) * 64 * ld + (size_t)j * 64, ld);
+    } else {
+      tile_fetch(ra, Li + (size_t)i * 64 * ld + (size_t)i * 64, ld);
+    }
+    mf_mac(acc, As, Bs);
     __syncthreads();
   }
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) Bs[4 * ty + r][4 * tx + c] = acc[r][c];
-  load_tile(As, Li + (size_t)i * 64 * ld + (size_t)i * 64, ld, false);
+  mf_each(acc, [&](int r, int c, double v) { Bs[r][c] = v; });
+  tile_put(As, ra, false);
   __syncthreads();
-  zero_acc(acc);
-  tile_mac(acc, As, Bs);
+  mf_zero(acc);
+  mf_mac(acc, As, Bs);
   double* p = Li + (size_t)i * 64 * ld + (size_t)j * 64;
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) p[(size_t)(4 * ty + r) * ld + 4 * tx + c] = -acc[r][c];
+  mf_each(acc, [&](int r, int c, double v) { p[(size_t)r * ld + c] = -v; });
 }
 
 // S^{-1}_ij = sum_{k >= max(i,j)} Li_ki^T Li_kj for i >= j, mirrored.
@@ -237,25 +279,29 @@ __global__ __launch_bounds__(256) void k_lauum(const double* Li, double* Sinv, i
   if (j > i) return;
   __shared__ Tile As;
   __shared__ Tile Bs;
-  double acc[4][4];
-  zero_acc(acc);
+  MfAcc acc;
+  mf_zero(acc);
+  // the tiles of step k + 1 are in flight while step k runs on the matrix cores
+  TileRegs ra, rb;
+  tile_fetch(ra, Li + (size_t)i * 64 * ld + (size_t)i * 64, ld);
+  tile_fetch(rb, Li + (size_t)i * 64 * ld + (size_t)j * 64, ld);
   for (int k = i; k < T; ++k) {
-    load_tile(As, Li + (size_t)k * 64 * ld + (size_t)i * 64, ld, true);
-    load_tile(Bs, Li + (size_t)k * 64 * ld + (size_t)j * 64, ld, false);
+    tile_put(As, ra, true);
+    tile_put(Bs, rb, false);
     __syncthreads();
-    tile_mac(acc, As, Bs);
+    if (k + 1 < T) {
+      tile_fetch(ra, Li + (size_t)(k + 1) * 64 * ld + (size_t)i * 64, ld);
+      tile_fetch(rb, Li + (size_t)(k + 1) * 64 * ld + (size_t)j * 64, ld);
+    }
+    mf_mac(acc, As, Bs);
     __syncthreads();
   }
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const size_t gr = (size_t)i * 64 + 4 * ty + r, gc = (size_t)j * 64 + 4 * tx + c;
-      if (gr < gc) continue;  // diagonal tile: the lower half defines both halves
-      Sinv[gr * ld + gc] = acc[r][c];
-      Sinv[gc * ld + gr] = acc[r][c];
-    }
+  mf_each(acc, [&](int r, int c, double v) {
+    const size_t gr = (size_t)i * 64 + r, gc = (size_t)j * 64 + c;
+    if (gr < gc) return;  // diagonal tile: the lower half defines both halves
+    Sinv[gr * ld + gc] = v;
+    Sinv[gc * ld + gr] = v;
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -302,8 +348,6 @@ __global__ __launch_bounds__(256) void k_iface_op(int NL, int ldS, const double*
 // A[l % 16][l / 16], B[l / 16][l % 16] and D[l / 16 + 4 v][l % 16], v < 4.
 // S^{-1} is read once (four coalesced 128-byte rows per load); the FMAs run
 // on the matrix cores, so 16 right-hand sides cost no more issue slots than 4.
-typedef double am_d4 __attribute__((ext_vector_type(4)));
-
 template <int NR>
 __global__ __launch_bounds__(256) void k_iface_op_mfma(int NL, int ldS, const double* __restrict__ Sinv,
                                                        const double* __restrict__ bpart,
