@@ -114,6 +114,29 @@ def test_mbf_and_interface_matrix_parity(name):
     h.close()
 
 
+def test_interface_inverse_many_tiles():
+    """Explicit S^-1 over 20 tiles of 64 (40 x 40 x 24 layered grid, 5 x 4 x 4
+    subdomains: NL = 1252, last tile ragged), so that the tiled Cholesky and
+    the triangular inverse run their loops over k up to 19 tiles long.  S
+    (condition ~4e5) against the oracle to 1e-12; S^-1 S = I to 1e-11 in max
+    norm; S^-1 within 1e-9 relative (cond(S) times a few units of rounding)
+    of numpy's inverse of the oracle's S; S^-1 exactly symmetric."""
+    P = make_config("c2", nx=40, ny=40, nz=24)
+    part, m = partition_blocks(P.dims, (5, 4, 4))
+    ora = AlgMortarCPU(P.A, part)
+    Sd = ora.S.toarray()
+    assert Sd.shape[0] == 1252
+    h = am.AlgMortar(P.A, part, m)
+    S = h.export_interface("S")
+    assert np.abs(S - Sd).max() <= 1e-12 * np.abs(Sd).max()
+    Si = h.export_interface("Sinv")
+    assert np.array_equal(Si, Si.T)
+    assert np.abs(Si @ Sd - np.eye(Sd.shape[0])).max() <= 1e-11
+    Sn = np.linalg.inv(Sd)
+    assert np.linalg.norm(Si - Sn) <= 1e-9 * np.linalg.norm(Sn)
+    h.close()
+
+
 @pytest.mark.parametrize("name", CASES)
 def test_apply_parity(name):
     A, part, m, b, ora = setup_case(name)
