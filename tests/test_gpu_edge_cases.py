@@ -1,0 +1,170 @@
+"""Edge cases of the HIP path against the FP64 oracle, through the C-ABI:
+zero right-hand sides (alone and as one column of a block), the smallest
+non-trivial problem (two cells, two subdomains), one-cell subdomains
+everywhere, a subdomain touching 100 mortar basis functions (accepted with
+one right-hand side, refused with eight), the set-up limits (130 basis
+functions on one subdomain, a subdomain whose bandwidth no ordering brings
+to 128) and a right-hand-side count beyond the handle's maximum."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+import paper_2607_22905_amd as am  # noqa: E402
+from paper_2607_22905_amd import AlgMortarError  # noqa: E402
+from oracle import AlgMortarCPU, partition_blocks, pcg  # noqa: E402
+from tests._problems import random_2d, random_3d  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def gpu(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=DEV)
+
+
+def cpu(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _ragged():
+    P = random_3d(18, 15, 8, 1.5, 11, block=(6, 5, 4))
+    part, m = partition_blocks(P.dims, P.partition[1])
+    return P, part, m
+
+
+def test_zero_rhs_alone():
+    P, part, m = _ragged()
+    h = am.AlgMortar(P.A, part, m)
+    z = cpu(h.apply(gpu(np.zeros(P.n))))
+    assert np.array_equal(z, np.zeros(P.n))
+    x, info, _ = h.pcg(gpu(np.zeros(P.n)), 1e-10)
+    assert np.array_equal(cpu(x), np.zeros(P.n))
+    assert info[0]["converged"] == 1 and info[0]["iterations"] == 0
+    assert info[0]["rel_res"] == 0.0 and info[0]["true_rel_res"] == 0.0
+    h.close()
+
+
+def test_zero_column_in_a_block():
+    """Column 1 of three is zero: it stops at iteration 0 with x = 0 while
+    the other two follow their own oracle solves."""
+    P, part, m = _ragged()
+    ora = AlgMortarCPU(P.A, part)
+    B = np.zeros((3, P.n))
+    B[0] = P.b
+    B[2] = np.random.default_rng(7).standard_normal(P.n)
+    h = am.AlgMortar(P.A, part, m, max_nrhs=4)
+    X, info, _ = h.pcg(gpu(B), 1e-10)
+    X = cpu(X)
+    assert np.array_equal(X[1], np.zeros(P.n))
+    assert info[1]["converged"] == 1 and info[1]["iterations"] == 0
+    for k in (0, 2):
+        res = pcg(lambda v: ora.As @ v, B[k], ora.apply, 1e-10)
+        assert info[k]["converged"] == 1
+        assert abs(info[k]["iterations"] - res.iterations) <= 1
+        assert rel(X[k], res.x) <= 1e-8
+    h.close()
+
+
+def test_two_cells_two_subdomains():
+    """2 x 1 grid, one cell per subdomain, one interface of one edge."""
+    P = random_2d(nx=2, ny=1, sigma=0.0, block=(1, 1, 1))
+    part, m = partition_blocks(P.dims, (1, 1, 1))
+    assert m == 2
+    ora = AlgMortarCPU(P.A, part)
+    h = am.AlgMortar(P.A, part, m)
+    r = np.array([0.7, -1.3])
+    assert rel(cpu(h.apply(gpu(r))), ora.apply(r)) <= 1e-12
+    x, info, _ = h.pcg(gpu(r), 1e-12)
+    xd = np.linalg.solve(ora.As.toarray(), r)
+    assert info[0]["converged"] == 1 and rel(cpu(x), xd) <= 1e-12
+    h.close()
+
+
+def test_one_cell_subdomains():
+    """4 x 4 x 3 grid, every cell its own subdomain (48 subdomains, 104
+    interfaces of one edge each)."""
+    P = random_3d(4, 4, 3, 1.0, 5, block=(1, 1, 1))
+    part, m = partition_blocks(P.dims, (1, 1, 1))
+    assert m == P.n
+    ora = AlgMortarCPU(P.A, part)
+    h = am.AlgMortar(P.A, part, m, max_nrhs=2)
+    R = np.random.default_rng(8).standard_normal((2, P.n))
+    Z = cpu(h.apply(gpu(R)))
+    for k in range(2):
+        assert rel(Z[k], ora.apply(R[k])) <= 1e-12
+    x, info, _ = h.pcg(gpu(P.b), 1e-10)
+    res = pcg(lambda v: ora.As @ v, P.b, ora.apply, 1e-10)
+    assert info[0]["converged"] == 1
+    assert abs(info[0]["iterations"] - res.iterations) <= 1
+    assert rel(cpu(x), res.x) <= 1e-8
+    h.close()
+
+
+def _comb(nx):
+    """nx x 2 grid: row 0 is one subdomain (a chain of nx cells), every cell
+    of row 1 is a subdomain of its own, so subdomain 0 touches nx mortar
+    basis functions (2 nx - 1 interfaces in all)."""
+    P = random_2d(nx=nx, ny=2, sigma=1.0, seed=3, block=(1, 1, 1))
+    k = np.arange(P.n)
+    x, y = k % nx, k // nx
+    part = np.where(y == 0, 0, 1 + x).astype(np.int32)
+    return P, part, nx + 1
+
+
+def test_subdomain_with_100_basis_functions():
+    P, part, m = _comb(100)
+    ora = AlgMortarCPU(P.A, part)
+    assert ora.st.n_iface == 199
+    assert int((np.asarray(ora.st.iface_ij) == 0).any(axis=1).sum()) == 100
+    h = am.AlgMortar(P.A, part, m)
+    rng = np.random.default_rng(9)
+    for _ in range(2):
+        r = rng.standard_normal(P.n)
+        assert rel(cpu(h.apply(gpu(r))), ora.apply(r)) <= 1e-12
+    b = rng.standard_normal(P.n)
+    x, info, _ = h.pcg(gpu(b), 1e-10)
+    res = pcg(lambda v: ora.As @ v, b, ora.apply, 1e-10)
+    assert info[0]["converged"] == 1
+    assert abs(info[0]["iterations"] - res.iterations) <= 1
+    assert rel(cpu(x), res.x) <= 1e-8
+    h.close()
+    with pytest.raises(AlgMortarError) as e:
+        am.AlgMortar(P.A, part, m, max_nrhs=8)
+    assert e.value.status_name == "AM_ERR_UNSUPPORTED"
+
+
+def test_setup_limits():
+    P, part, m = _comb(130)
+    with pytest.raises(AlgMortarError) as e:
+        am.AlgMortar(P.A, part, m)
+    assert e.value.status_name == "AM_ERR_UNSUPPORTED"
+    # a 20^3 block: every ordering leaves a bandwidth far above 128
+    Q = random_3d(20, 20, 20, 0.5, 2, block=(20, 20, 20))
+    part, m = partition_blocks(Q.dims, (20, 20, 20))
+    with pytest.raises(AlgMortarError) as e:
+        am.AlgMortar(Q.A, part, m)
+    assert e.value.status_name == "AM_ERR_UNSUPPORTED"
+
+
+def test_more_rhs_than_the_handle_allows():
+    P, part, m = _ragged()
+    h = am.AlgMortar(P.A, part, m, max_nrhs=2)
+    R = gpu(np.ones((3, P.n)))
+    with pytest.raises(AlgMortarError) as e:
+        h.apply(R)
+    assert e.value.status_name == "AM_ERR_ARG"
+    with pytest.raises(AlgMortarError) as e:
+        h.pcg(R, 1e-8)
+    assert e.value.status_name == "AM_ERR_ARG"
+    # the handle still works afterwards
+    r = np.random.default_rng(1).standard_normal(P.n)
+    ora = AlgMortarCPU(P.A, part)
+    assert rel(cpu(h.apply(gpu(r))), ora.apply(r)) <= 1e-12
+    h.close()
