@@ -491,17 +491,22 @@ static am_status setup_impl(const am_csr* A, const int32_t* part, int32_t nparts
   SCHK(launch_invert_diag(d, sm));
   SCHK(launch_assemble_S(d, sm));
   if (NL > 0) {
-    double *L = nullptr, *Li = nullptr;
+    double *L = nullptr, *Li = nullptr, *part = nullptr;
+    const int64_t ptiles = trtri_part_tiles(d.ldS / 64);
     SCHK(hipMalloc((void**)&L, nS * sizeof(double)));
     hipError_t he = hipMalloc((void**)&Li, nS * sizeof(double));
+    if (he == hipSuccess && ptiles > 0)
+      he = hipMalloc((void**)&part, (size_t)ptiles * 4096 * sizeof(double));
     if (he != hipSuccess) {
       hipFree(L);
-      return hipfail(he, "hipMalloc(L^-1)");
+      hipFree(Li);
+      return hipfail(he, "hipMalloc(interface inverse scratch)");
     }
-    he = dense_cholesky_inverse(d, L, Li, sm);
+    he = dense_cholesky_inverse(d, L, Li, part, sm);
     hipError_t he2 = hipStreamSynchronize(sm);
     hipFree(L);
     hipFree(Li);
+    hipFree(part);
     if (he != hipSuccess) return hipfail(he, "dense_cholesky_inverse");
     if (he2 != hipSuccess) return hipfail(he2, "interface factorization");
   }

@@ -150,7 +150,12 @@ hipError_t launch_bpart(DeviceState& d, const double* r, int nrhs, hipStream_t s
 
 // ---- launchers (kernels_iface.hip) ----
 hipError_t launch_assemble_S(DeviceState& d, hipStream_t s);
-hipError_t dense_cholesky_inverse(DeviceState& d, double* L, double* Linv, hipStream_t s);
+// S^{-1} through the tiled Cholesky factor L and its inverse Linv (both
+// ldS x ldS scratch); part: trtri_part_tiles(ldS / 64) tiles of 64 x 64
+// scratch for the split launches of the inverse (may be null if that is 0)
+int64_t trtri_part_tiles(int T);
+hipError_t dense_cholesky_inverse(DeviceState& d, double* L, double* Linv, double* part,
+                                  hipStream_t s);
 // eta = S^{-1} b; in PCG mode (pcg != 0) the launch first applies the stop
 // test to the ||r||^2 partials (init: records ||b||^2)
 hipError_t launch_iface_gemv(DeviceState& d, int nrhs, int pcg, int init, hipStream_t s);

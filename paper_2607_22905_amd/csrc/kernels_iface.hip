@@ -273,6 +273,62 @@ __global__ __launch_bounds__(256) void k_trtri_off(const double* L, double* Li, 
   mf_each(acc, [&](int r, int c, double v) { p[(size_t)r * ld + c] = -v; });
 }
 
+// The sum of k_trtri_off split over nchunk workgroups per tile, for the
+// launches with few tiles: workgroup (j, c) forms the share
+//   part[j nchunk + c] = sum_{k = k0}^{k1 - 1} L_ik Li_kj,
+// k0 = j + c d / nchunk, k1 = j + (c + 1) d / nchunk, as a row-major 64 x 64
+// block (nchunk <= d, so no share is empty).
+__global__ __launch_bounds__(256) void k_trtri_part(const double* L, const double* Li, int ld,
+                                                    int d, int nchunk, double* part) {
+  const int j = blockIdx.x / nchunk, c = blockIdx.x % nchunk, i = j + d;
+  const int k0 = j + (int)((int64_t)c * d / nchunk);
+  const int k1 = j + (int)((int64_t)(c + 1) * d / nchunk);
+  __shared__ Tile As;
+  __shared__ Tile Bs;
+  MfAcc acc;
+  mf_zero(acc);
+  TileRegs ra, rb;
+  tile_fetch(ra, L + (size_t)i * 64 * ld + (size_t)k0 * 64, ld);
+  tile_fetch(rb, Li + (size_t)k0 * 64 * ld + (size_t)j * 64, ld);
+  for (int k = k0; k < k1; ++k) {
+    tile_put(As, ra, false);
+    tile_put(Bs, rb, false);
+    __syncthreads();
+    if (k + 1 < k1) {
+      tile_fetch(ra, L + (size_t)i * 64 * ld + (size_t)(k + 1) * 64, ld);
+      tile_fetch(rb, Li + (size_t)(k + 1) * 64 * ld + (size_t)j * 64, ld);
+    }
+    mf_mac(acc, As, Bs);
+    __syncthreads();
+  }
+  double* p = part + (size_t)blockIdx.x * 4096;
+  mf_each(acc, [&](int r, int cc, double v) { p[r * 64 + cc] = v; });
+}
+
+// Li_ij = -Li_ii sum_c part[j nchunk + c], the shares added in order c = 0, 1, ..
+__global__ __launch_bounds__(256) void k_trtri_fin(double* Li, int ld, int d, int nchunk,
+                                                   const double* part) {
+  const int j = blockIdx.x, i = j + d;
+  __shared__ Tile As;
+  __shared__ Tile Bs;
+  TileRegs sum, t;
+  tile_fetch(sum, part + (size_t)j * nchunk * 4096, 64);
+  for (int c = 1; c < nchunk; ++c) {
+    tile_fetch(t, part + ((size_t)j * nchunk + c) * 4096, 64);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) sum.v[u] += t.v[u];
+  }
+  tile_put(Bs, sum, false);
+  tile_fetch(t, Li + (size_t)i * 64 * ld + (size_t)i * 64, ld);
+  tile_put(As, t, false);
+  __syncthreads();
+  MfAcc acc;
+  mf_zero(acc);
+  mf_mac(acc, As, Bs);
+  double* p = Li + (size_t)i * 64 * ld + (size_t)j * 64;
+  mf_each(acc, [&](int r, int c, double v) { p[(size_t)r * ld + c] = -v; });
+}
+
 // S^{-1}_ij = sum_{k >= max(i,j)} Li_ki^T Li_kj for i >= j, mirrored.
 __global__ __launch_bounds__(256) void k_lauum(const double* Li, double* Sinv, int ld, int T) {
   const int j = blockIdx.x, i = blockIdx.y;
@@ -462,7 +518,25 @@ hipError_t launch_assemble_S(DeviceState& d, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t dense_cholesky_inverse(DeviceState& d, double* L, double* Li, hipStream_t st) {
+// Shares per tile of the distance-d launch of the triangular inverse: enough
+// workgroups for two per CU, at most 16 shares, none empty.
+int trtri_chunks(int T, int d) {
+  const int nb = T - d;
+  return std::max(1, std::min(std::min(16, d), 512 / nb));
+}
+
+// Scratch tiles the split launches need (0 if none is split).
+int64_t trtri_part_tiles(int T) {
+  int64_t mx = 0;
+  for (int dd = 1; dd < T; ++dd) {
+    const int c = trtri_chunks(T, dd);
+    if (c > 1) mx = std::max<int64_t>(mx, (int64_t)(T - dd) * c);
+  }
+  return mx;
+}
+
+hipError_t dense_cholesky_inverse(DeviceState& d, double* L, double* Li, double* part,
+                                  hipStream_t st) {
   const int ld = d.ldS, T = ld / 64;
   if (T == 0) return hipSuccess;
   hipError_t e = hipMemcpyAsync(L, d.S, sizeof(double) * (size_t)ld * ld, hipMemcpyDeviceToDevice, st);
@@ -477,8 +551,15 @@ hipError_t dense_cholesky_inverse(DeviceState& d, double* L, double* Li, hipStre
     }
   }
   hipLaunchKernelGGL(k_trtri_diag, dim3(T), dim3(64), 0, st, L, Li, ld);
-  for (int dd = 1; dd < T; ++dd)
-    hipLaunchKernelGGL(k_trtri_off, dim3(T - dd), dim3(256), 0, st, L, Li, ld, dd);
+  for (int dd = 1; dd < T; ++dd) {
+    const int c = trtri_chunks(T, dd);
+    if (c == 1) {
+      hipLaunchKernelGGL(k_trtri_off, dim3(T - dd), dim3(256), 0, st, L, Li, ld, dd);
+    } else {
+      hipLaunchKernelGGL(k_trtri_part, dim3((T - dd) * c), dim3(256), 0, st, L, Li, ld, dd, c, part);
+      hipLaunchKernelGGL(k_trtri_fin, dim3(T - dd), dim3(256), 0, st, Li, ld, dd, c, part);
+    }
+  }
   hipLaunchKernelGGL(k_lauum, dim3(T, T), dim3(256), 0, st, Li, d.Sinv, ld, T);
   return hipGetLastError();
 }
