@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -227,6 +228,19 @@ static am_status setup_impl(const am_csr* A, const int32_t* part, int32_t nparts
     g_err = msg;
     return s;
   };
+  // optional phase times on stderr (environment ALGMORTAR_SETUP_TIMES set):
+  // a phase that queued device work ends with a stream synchronisation, so
+  // the work is charged to it
+  const bool ptimes = std::getenv("ALGMORTAR_SETUP_TIMES") != nullptr;
+  std::vector<std::pair<const char*, double>> phases;
+  auto t_last = std::chrono::steady_clock::now();
+  auto mark = [&](const char* name, hipStream_t sync) {
+    if (!ptimes) return;
+    if (sync) (void)hipStreamSynchronize(sync);
+    const auto t = std::chrono::steady_clock::now();
+    phases.emplace_back(name, std::chrono::duration<double, std::milli>(t - t_last).count());
+    t_last = t;
+  };
   HostCSR H;
   std::vector<double> vals;
   if (A && A->values_on_device) {
@@ -237,12 +251,15 @@ static am_status setup_impl(const am_csr* A, const int32_t* part, int32_t nparts
   }
   am_status s = host_csr(A, H, vals, h);
   if (s != AM_OK) return bail(s);
+  mark("host copy of A", nullptr);
   std::string e;
   if ((s = validate_csr(H, e)) != AM_OK) { fail(h, s, e); return bail(s); }
   if ((s = validate_partition(H.n, part, nparts, e)) != AM_OK) { fail(h, s, e); return bail(s); }
+  mark("validation", nullptr);
   Structure& st = h->st;
   LocalPlan& lp = h->lp;
   if ((s = build_structure(H, part, nparts, opt.mortar, st, e)) != AM_OK) { fail(h, s, e); return bail(s); }
+  mark("interface structure", nullptr);
   if (plain) {
     st.edge_k.clear();
     st.edge_l.clear();
@@ -253,6 +270,7 @@ static am_status setup_impl(const am_csr* A, const int32_t* part, int32_t nparts
     st.isub_list.clear();
   }
   if ((s = plan_local(H, st, lp, e)) != AM_OK) { fail(h, s, e); return bail(s); }
+  mark("local orderings", nullptr);
   if (lp.max_ni > 128) {
     fail(h, AM_ERR_UNSUPPORTED, "a subdomain touches more than 128 mortar basis functions");
     return bail(AM_ERR_UNSUPPORTED);
@@ -302,6 +320,7 @@ static am_status setup_impl(const am_csr* A, const int32_t* part, int32_t nparts
   SCHK(hipEventCreateWithFlags(&h->evf[1], hipEventDisableTiming));
   hipStream_t sm = h->own;
   if (stream) SCHK(hipStreamSynchronize((hipStream_t)stream));
+  mark("device context", nullptr);
 
   // ---- host-side layout ----
   const int64_t n = d.n;
@@ -311,9 +330,16 @@ static am_status setup_impl(const am_csr* A, const int32_t* part, int32_t nparts
   std::vector<int32_t> pci((size_t)H.nnz);
   std::vector<double> pv((size_t)H.nnz);
   int32_t w = 0;
-  {
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t o = dperm[i];
+    prp[i + 1] = prp[i] + (H.rp[o + 1] - H.rp[o]);
+    w = std::max<int32_t>(w, (int32_t)(H.rp[o + 1] - H.rp[o]));
+  }
+  // rows of A in device order, columns ascending (each row its own range)
+  parallel_for((n + 1023) / 1024, 1, [&](int64_t c) {
     std::vector<std::pair<int32_t, double>> row;
-    for (int64_t i = 0; i < n; ++i) {
+    const int64_t hi = std::min<int64_t>(n, (c + 1) * 1024);
+    for (int64_t i = c * 1024; i < hi; ++i) {
       const int64_t o = dperm[i];
       row.clear();
       for (int64_t p = H.rp[o]; p < H.rp[o + 1]; ++p) row.emplace_back(dpos[H.ci[p]], H.v[p]);
@@ -321,27 +347,28 @@ static am_status setup_impl(const am_csr* A, const int32_t* part, int32_t nparts
                 [](const std::pair<int32_t, double>& a, const std::pair<int32_t, double>& b) {
                   return a.first < b.first;
                 });
-      prp[i + 1] = prp[i] + (int64_t)row.size();
       for (size_t t = 0; t < row.size(); ++t) {
         pci[prp[i] + t] = row[t].first;
         pv[prp[i] + t] = row[t].second;
       }
-      w = std::max<int32_t>(w, (int32_t)row.size());
     }
-  }
+  });
   d.ell_w = w;
   std::vector<int32_t> ell_col((size_t)w * n);
   std::vector<double> ell_val((size_t)w * n, 0.0);
-  for (int64_t i = 0; i < n; ++i)
-    for (int32_t c = 0; c < w; ++c) {
-      const int64_t p = prp[i] + c;
-      if (p < prp[i + 1]) {
-        ell_col[(size_t)c * n + i] = pci[p];
-        ell_val[(size_t)c * n + i] = pv[p];
-      } else {
-        ell_col[(size_t)c * n + i] = (int32_t)i;
+  parallel_for((n + 4095) / 4096, 1, [&](int64_t cb) {
+    const int64_t hi = std::min<int64_t>(n, (cb + 1) * 4096);
+    for (int64_t i = cb * 4096; i < hi; ++i)
+      for (int32_t c = 0; c < w; ++c) {
+        const int64_t p = prp[i] + c;
+        if (p < prp[i + 1]) {
+          ell_col[(size_t)c * n + i] = pci[p];
+          ell_val[(size_t)c * n + i] = pv[p];
+        } else {
+          ell_col[(size_t)c * n + i] = (int32_t)i;
+        }
       }
-    }
+  });
   for (int bk = 0; bk < 2; ++bk) d.bucket_sub[bk].clear();
   for (int32_t s2 = 0; s2 < st.m; ++s2) d.bucket_sub[lp.wp[s2] == 64 ? 0 : 1].push_back(s2);
 
@@ -401,6 +428,8 @@ static am_status setup_impl(const am_csr* A, const int32_t* part, int32_t nparts
     std::vector<std::pair<int32_t, double>>().swap(v);
   }
 
+  mark("host layout", nullptr);
+
   // ---- device upload ----
   std::vector<void*>& al = d.allocs;
   SCHK(upload(al, &d.dperm, dperm, sm));
@@ -433,6 +462,7 @@ static am_status setup_impl(const am_csr* A, const int32_t* part, int32_t nparts
   SCHK(upload(al, &d.bdst, bdst, sm));
   std::vector<double>().swap(ell_val);
   std::vector<int32_t>().swap(ell_col);
+  mark("uploads", sm);
 
   const size_t esz = d.prec == AM_FP64 ? 8 : (d.prec == AM_FP32 ? 4 : 2);
   const size_t isz = d.prec == AM_FP64 ? 8 : 4;
@@ -484,12 +514,18 @@ static am_status setup_impl(const am_csr* A, const int32_t* part, int32_t nparts
   SCHK(hipMemsetAsync(d.shared, 0, sizeof(PcgShared), sm));
   SCHK(hipHostMalloc((void**)&d.h_flags, 4 * sizeof(int32_t), hipHostMallocDefault));
 
+  mark("device allocations", sm);
+
   // ---- Algorithm 1 on the device ----
   SCHK(launch_band_factor(d, sm));
+  mark("local factors", sm);
   SCHK(launch_mbf(d, sm));
+  mark("basis functions", sm);
   // solve-time form of the factor: inverted diagonal blocks, column layout only
   SCHK(launch_invert_diag(d, sm));
+  mark("diagonal block inverses", sm);
   SCHK(launch_assemble_S(d, sm));
+  mark("interface matrix S", sm);
   if (NL > 0) {
     double *L = nullptr, *Li = nullptr, *part = nullptr;
     const int64_t ptiles = trtri_part_tiles(d.ldS / 64);
@@ -509,6 +545,7 @@ static am_status setup_impl(const am_csr* A, const int32_t* part, int32_t nparts
     hipFree(part);
     if (he != hipSuccess) return hipfail(he, "dense_cholesky_inverse");
     if (he2 != hipSuccess) return hipfail(he2, "interface factorization");
+    mark("interface inverse", nullptr);
   }
   SCHK(hipStreamSynchronize(sm));
   int32_t fl[4];
@@ -531,6 +568,8 @@ static am_status setup_impl(const am_csr* A, const int32_t* part, int32_t nparts
       break;
     }
   d.Lr = nullptr;
+  mark("checks and frees", nullptr);
+  for (const auto& ph : phases) std::fprintf(stderr, "algmortar set-up: %-24s %9.2f ms\n", ph.first, ph.second);
   *out = h;
   return AM_OK;
 #undef SCHK

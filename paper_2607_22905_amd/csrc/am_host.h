@@ -3,13 +3,48 @@
 // device-oriented layout plan derived from them.  Plain C++17, no HIP.
 #pragma once
 
+#include <algorithm>
+
+#include <atomic>
 #include <cstdint>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "algmortar.h"
 
 namespace am {
+
+// Host threads for the set-up loops: ALGMORTAR_HOST_THREADS if set, else the
+// hardware threads, at most 16.
+int host_threads();
+
+// Runs f(i) for every i in [0, n) on up to host_threads() threads (the
+// caller's included), handing out chunks of `grain` indices in increasing
+// order.  f must write only data that belongs to its own index; results are
+// then independent of the thread count and the schedule.
+template <typename F>
+void parallel_for(int64_t n, int64_t grain, F&& f) {
+  const int nt = (int)std::min<int64_t>(host_threads(), (n + grain - 1) / grain);
+  if (nt <= 1) {
+    for (int64_t i = 0; i < n; ++i) f(i);
+    return;
+  }
+  std::atomic<int64_t> next{0};
+  auto work = [&]() {
+    for (;;) {
+      const int64_t lo = next.fetch_add(grain);
+      if (lo >= n) return;
+      const int64_t hi = std::min(n, lo + grain);
+      for (int64_t i = lo; i < hi; ++i) f(i);
+    }
+  };
+  std::vector<std::thread> pool;
+  pool.reserve(nt - 1);
+  for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+  work();
+  for (auto& th : pool) th.join();
+}
 
 struct HostCSR {
   int64_t n = 0, nnz = 0;

@@ -4,6 +4,7 @@
 // numbering and I_i, and the local band-ordering plan used by the device.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <tuple>
@@ -21,6 +22,15 @@ static bool find_entry(const HostCSR& A, int64_t row, int32_t col, double* v) {
   return true;
 }
 
+int host_threads() {
+  if (const char* e = std::getenv("ALGMORTAR_HOST_THREADS")) {
+    const int v = std::atoi(e);
+    if (v >= 1) return std::min(v, 256);
+  }
+  const unsigned hw = std::thread::hardware_concurrency();
+  return (int)std::max(1u, std::min(hw, 16u));
+}
+
 am_status validate_csr(const HostCSR& A, std::string& err) {
   if (A.n <= 0 || A.n > INT32_MAX || !A.rp || !A.ci || !A.v) {
     err = "A: null pointer or n out of range";
@@ -30,26 +40,76 @@ am_status validate_csr(const HostCSR& A, std::string& err) {
     err = "A: row_ptr[0] must be 0 and row_ptr[n] must equal nnz";
     return AM_ERR_ARG;
   }
-  for (int64_t k = 0; k < A.n; ++k) {
+  // Each pass checks rows in parallel; the error reported is that of the
+  // lowest failing row, as a row-by-row scan would find it.
+  constexpr int64_t kGrain = 4096;
+  const int64_t nch = (A.n + kGrain - 1) / kGrain;
+  std::vector<int64_t> bad_row(nch, -1);
+  std::vector<am_status> bad_code(nch, AM_OK);
+  auto first_bad = [&]() -> int64_t {
+    for (int64_t c = 0; c < nch; ++c)
+      if (bad_row[c] >= 0) return c;
+    return -1;
+  };
+  // pass 1: pattern, finiteness, diagonal
+  auto row_ok = [&](int64_t k, am_status& code) -> bool {
+    if (A.rp[k + 1] < A.rp[k]) {
+      code = AM_ERR_ARG;
+      return false;
+    }
+    bool diag = false;
+    for (int64_t p = A.rp[k]; p < A.rp[k + 1]; ++p) {
+      const int32_t c = A.ci[p];
+      if (c < 0 || c >= A.n || (p > A.rp[k] && c <= A.ci[p - 1]) || !std::isfinite(A.v[p])) {
+        code = AM_ERR_ARG;
+        return false;
+      }
+      if (c == k) {
+        diag = true;
+        if (!(A.v[p] > 0)) {
+          code = AM_ERR_NOT_SPD;
+          return false;
+        }
+      }
+    }
+    if (!diag) {
+      code = AM_ERR_NOT_SPD;
+      return false;
+    }
+    return true;
+  };
+  parallel_for(nch, 1, [&](int64_t c) {
+    const int64_t hi = std::min(A.n, (c + 1) * kGrain);
+    for (int64_t k = c * kGrain; k < hi; ++k) {
+      am_status code = AM_OK;
+      if (!row_ok(k, code)) {
+        bad_row[c] = k;
+        bad_code[c] = code;
+        return;
+      }
+    }
+  });
+  if (int64_t c = first_bad(); c >= 0) {
+    // rebuild the message of the failing row serially
+    const int64_t k = bad_row[c];
     if (A.rp[k + 1] < A.rp[k]) {
       err = "A: row_ptr not monotone at row " + std::to_string(k);
       return AM_ERR_ARG;
     }
     bool diag = false;
     for (int64_t p = A.rp[k]; p < A.rp[k + 1]; ++p) {
-      int32_t c = A.ci[p];
-      if (c < 0 || c >= A.n || (p > A.rp[k] && c <= A.ci[p - 1])) {
+      const int32_t cc = A.ci[p];
+      if (cc < 0 || cc >= A.n || (p > A.rp[k] && cc <= A.ci[p - 1])) {
         err = "A: columns must be in range and strictly ascending (row " + std::to_string(k) + ")";
         return AM_ERR_ARG;
       }
-      double v = A.v[p];
-      if (!std::isfinite(v)) {
+      if (!std::isfinite(A.v[p])) {
         err = "A: non-finite value at row " + std::to_string(k);
         return AM_ERR_ARG;
       }
-      if (c == k) {
+      if (cc == k) {
         diag = true;
-        if (!(v > 0)) {
+        if (!(A.v[p] > 0)) {
           err = "A: nonpositive diagonal at row " + std::to_string(k);
           return AM_ERR_NOT_SPD;
         }
@@ -59,24 +119,39 @@ am_status validate_csr(const HostCSR& A, std::string& err) {
       err = "A: missing diagonal at row " + std::to_string(k);
       return AM_ERR_NOT_SPD;
     }
+    err = "A: invalid row " + std::to_string(k);
+    return bad_code[c];
   }
-  for (int64_t k = 0; k < A.n; ++k) {
-    for (int64_t p = A.rp[k]; p < A.rp[k + 1]; ++p) {
-      int32_t c = A.ci[p];
-      if (c == k) continue;
-      double v = A.v[p], t = 0.0;
-      bool has = find_entry(A, c, (int32_t)k, &t);
-      if (!has) t = 0.0;
-      if (std::memcmp(&v, &t, sizeof(double)) != 0 && !(v == 0.0 && t == 0.0)) {
-        err = "A not symmetric at (" + std::to_string(k) + "," + std::to_string(c) + ")";
-        return AM_ERR_NOT_SYMMETRIC;
+  // pass 2: bitwise symmetry and the sign of the couplings
+  std::vector<int64_t> bad_p(nch, -1);
+  parallel_for(nch, 1, [&](int64_t c) {
+    const int64_t hi = std::min(A.n, (c + 1) * kGrain);
+    for (int64_t k = c * kGrain; k < hi; ++k)
+      for (int64_t p = A.rp[k]; p < A.rp[k + 1]; ++p) {
+        const int32_t cc = A.ci[p];
+        if (cc == k) continue;
+        double v = A.v[p], t = 0.0;
+        if (!find_entry(A, cc, (int32_t)k, &t)) t = 0.0;
+        const bool asym = std::memcmp(&v, &t, sizeof(double)) != 0 && !(v == 0.0 && t == 0.0);
+        if (asym || v > 0) {
+          bad_row[c] = k;
+          bad_p[c] = p;
+          return;
+        }
       }
-      if (v > 0) {
-        err = "positive off-diagonal at (" + std::to_string(k) + "," + std::to_string(c) +
-              "): interface weights must be negative";
-        return AM_ERR_POSITIVE_COUPLING;
-      }
+  });
+  if (int64_t c = first_bad(); c >= 0) {
+    const int64_t k = bad_row[c], p = bad_p[c];
+    const int32_t cc = A.ci[p];
+    double v = A.v[p], t = 0.0;
+    if (!find_entry(A, cc, (int32_t)k, &t)) t = 0.0;
+    if (std::memcmp(&v, &t, sizeof(double)) != 0 && !(v == 0.0 && t == 0.0)) {
+      err = "A not symmetric at (" + std::to_string(k) + "," + std::to_string(cc) + ")";
+      return AM_ERR_NOT_SYMMETRIC;
     }
+    err = "positive off-diagonal at (" + std::to_string(k) + "," + std::to_string(cc) +
+          "): interface weights must be negative";
+    return AM_ERR_POSITIVE_COUPLING;
   }
   return AM_OK;
 }
@@ -305,14 +380,16 @@ am_status partition_bisect(const HostCSR& A, int32_t lo, int32_t hi, uint64_t se
 // Local ordering plan.
 namespace {
 
+// Cells of subdomain s are those with part[c] == s; loc[c] is their local
+// index (written only for them, so subdomains can be planned concurrently).
 int64_t bandwidth(const HostCSR& A, const std::vector<int32_t>& cells,
-                  const std::vector<int32_t>& loc) {
+                  const std::vector<int32_t>& loc, const int32_t* part, int32_t s) {
   int64_t bw = 0;
   for (size_t t = 0; t < cells.size(); ++t) {
     int64_t g = cells[t];
     for (int64_t p = A.rp[g]; p < A.rp[g + 1]; ++p) {
       int32_t c = A.ci[p];
-      if (c == g || A.v[p] == 0.0 || loc[c] < 0) continue;
+      if (c == g || A.v[p] == 0.0 || part[c] != s) continue;
       bw = std::max<int64_t>(bw, std::abs((int64_t)loc[c] - (int64_t)t));
     }
   }
@@ -324,7 +401,7 @@ int64_t bandwidth(const HostCSR& A, const std::vector<int32_t>& cells,
 // vertex (farthest from the component's smallest member, ties to the
 // smallest degree then index); neighbours enqueued by (degree, index).
 std::vector<int32_t> rcm(const HostCSR& A, const std::vector<int32_t>& cells,
-                         std::vector<int32_t>& loc) {
+                         const std::vector<int32_t>& loc, const int32_t* part, int32_t s) {
   const int32_t ns = (int32_t)cells.size();
   std::vector<int32_t> deg(ns, 0);
   std::vector<std::vector<int32_t>> adj(ns);
@@ -332,7 +409,7 @@ std::vector<int32_t> rcm(const HostCSR& A, const std::vector<int32_t>& cells,
     int64_t g = cells[t];
     for (int64_t p = A.rp[g]; p < A.rp[g + 1]; ++p) {
       int32_t c = A.ci[p];
-      if (c == g || A.v[p] == 0.0 || loc[c] < 0) continue;
+      if (c == g || A.v[p] == 0.0 || part[c] != s) continue;
       adj[t].push_back(loc[c]);
     }
     deg[t] = (int32_t)adj[t].size();
@@ -393,27 +470,38 @@ am_status plan_local(const HostCSR& A, const Structure& st, LocalPlan& lp, std::
   lp.max_ni = 0;
   lp.max_sub = 0;
   std::vector<int32_t> loc(n, -1);
-  for (int32_t s = 0; s < st.m; ++s) {
+  std::vector<int64_t> bws(st.m, 0);
+  const int32_t* part = st.part.data();
+  // each subdomain independently (its own cells of loc, dperm and dpos)
+  parallel_for(st.m, 8, [&](int64_t s64) {
+    const int32_t s = (int32_t)s64;
     const int64_t b = st.sub_ptr[s], e = st.sub_ptr[s + 1];
     std::vector<int32_t> cells(st.perm.begin() + b, st.perm.begin() + e);
     const int32_t ns = (int32_t)cells.size();
     for (int32_t t = 0; t < ns; ++t) loc[cells[t]] = t;
-    int64_t bw_id = bandwidth(A, cells, loc);
+    const int64_t bw_id = bandwidth(A, cells, loc, part, s);
     std::vector<int32_t> chosen = cells;
     int64_t bw = bw_id;
     if (bw_id > 64) {
-      std::vector<int32_t> ord = rcm(A, cells, loc);
+      std::vector<int32_t> ord = rcm(A, cells, loc, part, s);
       std::vector<int32_t> rc(ns);
       for (int32_t t = 0; t < ns; ++t) rc[t] = cells[ord[t]];
-      for (int32_t t = 0; t < ns; ++t) loc[cells[t]] = -1;
       for (int32_t t = 0; t < ns; ++t) loc[rc[t]] = t;
-      int64_t bw_rc = bandwidth(A, rc, loc);
+      const int64_t bw_rc = bandwidth(A, rc, loc, part, s);
       if (bw_rc < bw_id) {
         chosen = rc;
         bw = bw_rc;
       }
     }
-    for (int32_t t = 0; t < ns; ++t) loc[cells[t]] = -1;
+    bws[s] = bw;
+    for (int32_t t = 0; t < ns; ++t) {
+      lp.dperm[b + t] = chosen[t];
+      lp.dpos[chosen[t]] = (int32_t)(b + t);
+    }
+  });
+  for (int32_t s = 0; s < st.m; ++s) {
+    const int64_t bw = bws[s];
+    const int32_t ns = (int32_t)(st.sub_ptr[s + 1] - st.sub_ptr[s]);
     int32_t wp = 64 * (int32_t)std::max<int64_t>(1, (bw + 63) / 64);
     if (wp > 128) {
       err = "subdomain " + std::to_string(s) + " has local bandwidth " + std::to_string(bw) +
@@ -427,10 +515,6 @@ am_status plan_local(const HostCSR& A, const Structure& st, LocalPlan& lp, std::
     const int64_t np = ((int64_t)ns + 63) / 64 * 64;
     lp.roff[s + 1] = lp.roff[s] + np;
     lp.fac_off[s + 1] = lp.fac_off[s] + np * wp;
-    for (int32_t t = 0; t < ns; ++t) {
-      lp.dperm[b + t] = chosen[t];
-      lp.dpos[chosen[t]] = (int32_t)(b + t);
-    }
   }
   return AM_OK;
 }
