@@ -158,7 +158,12 @@ am_status am_structure(const am_csr* A, const int32_t* part, int32_t nparts, int
  * A: see am_csr; part: host int32[n] with ids in [0, nparts), none empty.
  * opt: host (NULL = defaults: FP64, per-interface mortar, 1 RHS, device 0).
  * On success *out owns all device memory until algmortar_destroy.
- * AM_ERR_NOT_SPD names the subdomain and pivot that failed. */
+ * AM_ERR_NOT_SPD names the subdomain and pivot that failed.  The host part
+ * (validation, local orderings, device-order rows) runs on up to 16 host
+ * threads, or ALGMORTAR_HOST_THREADS if that is set; results do not depend on
+ * the thread count, and an error names the lowest failing row or subdomain.
+ * With ALGMORTAR_SETUP_TIMES set, the time of each set-up phase is printed
+ * to stderr (phases with device work then end with a synchronization). */
 am_status algmortar_setup(const am_csr* A, const int32_t* part, int32_t nparts,
                           const am_options* opt, void* stream, am_handle* out);
 
