@@ -365,8 +365,10 @@ __global__ __launch_bounds__(256) void k_lauum(const double* Li, double* Sinv, i
 // over the rows of the symmetric S^{-1}: eta[r] = sum_m S^{-1}[m][r] b_m.
 // Wave (rb, p) takes the 64 entries r = 64 rb + lane and the rows m of part
 // p: each row is one coalesced 64-value load and NR FMAs with b_m, a uniform
-// (scalar) load, so S^{-1} is read exactly once per product.  The part sums
-// go to ypart[p][r][k]; k_iface_reduce adds them in part order.
+// (scalar) load, so S^{-1} is read exactly once per product.  The loads are
+// non-temporal: S^{-1} is streamed once per product and would otherwise evict
+// the vectors and the SpMV arrays from L2 and the Infinity Cache.  The part
+// sums go to ypart[p][r][k]; k_iface_reduce adds them in part order.
 template <int NR>
 __global__ __launch_bounds__(256) void k_iface_op(int NL, int ldS, const double* __restrict__ Sinv,
                                                   const double* __restrict__ bpart,
@@ -387,7 +389,7 @@ __global__ __launch_bounds__(256) void k_iface_op(int NL, int ldS, const double*
   for (int k = 0; k < NR; ++k) acc[k] = 0.0;
 #pragma unroll 8
   for (int m = mb; m < me; ++m) {
-    const double sv = col[(size_t)m * ldS];
+    const double sv = __builtin_nontemporal_load(col + (size_t)m * ldS);
 #pragma unroll
     for (int k = 0; k < NR; ++k)
       acc[k] = fma(sv, bpart[(size_t)(2 * m) * NR + k] + bpart[(size_t)(2 * m + 1) * NR + k], acc[k]);
@@ -402,8 +404,9 @@ __global__ __launch_bounds__(256) void k_iface_op(int NL, int ldS, const double*
 // so the rows m of S^{-1} stand for its columns) and B = b[m0 .. m0+3][NR
 // columns, zero-padded to 16].  v_mfma_f64_16x16x4_f64 lane l holds
 // A[l % 16][l / 16], B[l / 16][l % 16] and D[l / 16 + 4 v][l % 16], v < 4.
-// S^{-1} is read once (four coalesced 128-byte rows per load); the FMAs run
-// on the matrix cores, so 16 right-hand sides cost no more issue slots than 4.
+// S^{-1} is read once (four coalesced 128-byte rows per load, non-temporal
+// as in k_iface_op); the FMAs run on the matrix cores, so 16 right-hand sides
+// cost no more issue slots than 4.
 template <int NR>
 __global__ __launch_bounds__(256) void k_iface_op_mfma(int NL, int ldS, const double* __restrict__ Sinv,
                                                        const double* __restrict__ bpart,
@@ -436,7 +439,7 @@ __global__ __launch_bounds__(256) void k_iface_op_mfma(int NL, int ldS, const do
                   ? bpart[(size_t)(2 * m) * NR + li] + bpart[(size_t)(2 * m + 1) * NR + li]
                   : 0.0;
 #pragma unroll
-      for (int sub = 0; sub < 4; ++sub) av[u][sub] = ok ? col[(size_t)m * ldS + 16 * sub] : 0.0;
+      for (int sub = 0; sub < 4; ++sub) av[u][sub] = ok ? __builtin_nontemporal_load(col + (size_t)m * ldS + 16 * sub) : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
