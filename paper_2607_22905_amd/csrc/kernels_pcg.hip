@@ -503,11 +503,22 @@ hipError_t launch_pcg_init(DeviceState& d, int nr, double tol, int maxit, int fl
   return hipGetLastError();
 }
 
+// Workgroups per column group of the SpMV launch (and so its (p, Ap)
+// partials per column): the total stays at spmv_blocks whatever the number
+// of groups.  Every workgroup folds all the (r, z) partials of its group,
+// and every update workgroup all the (p, Ap) partials, so more workgroups
+// per group would only repeat that traffic; the sequence of dependent row
+// sweeps per SIMD is the same either way.
+template <int NR>
+static int spmv_group_blocks(const DeviceState& d) {
+  return std::max(1, d.red.spmv_blocks / (NR / KGroup<NR>::v));
+}
+
 static hipError_t update_xr(DeviceState& d, int nr, int parity, int init, hipStream_t s) {
   const double* pn = d.p[1 - parity];
   AM_NR_SWITCH(nr, hipLaunchKernelGGL(k_update_xr<NR>, dim3(d.m * (NR / KGroup<NR>::v)), dim3(256), 0, s, d.n, d.sub_ptr,
                                       d.isub_ptr, d.mbf_off, d.mbf, d.bdst, pn, d.q, d.x, d.r,
-                                      d.bpart, d.red.pa, d.red.spmv_blocks, d.red.pb, d.sc,
+                                      d.bpart, d.red.pa, spmv_group_blocks<NR>(d), d.red.pb, d.sc,
                                       d.shared, init, parity));
   return hipGetLastError();
 }
@@ -530,11 +541,11 @@ hipError_t launch_pcg_spmv(DeviceState& d, int nr, int parity, hipStream_t s) {
   const double* po = d.p[parity];
   double* pn = d.p[1 - parity];
   if (d.ell_w <= 8) {
-    AM_NR_SWITCH(nr, hipLaunchKernelGGL((k_spmv_p<NR, 8>), dim3(d.red.spmv_blocks * (NR / KGroup<NR>::v)), dim3(256), 0, s,
+    AM_NR_SWITCH(nr, hipLaunchKernelGGL((k_spmv_p<NR, 8>), dim3(spmv_group_blocks<NR>(d) * (NR / KGroup<NR>::v)), dim3(256), 0, s,
                                         d.n, d.ell_w, d.ell_col, d.ell_val, d.z, po, pn, d.q,
                                         d.red.pd, d.m, d.red.pa, d.sc, d.shared, parity));
   } else {
-    AM_NR_SWITCH(nr, hipLaunchKernelGGL((k_spmv_p<NR, 32>), dim3(d.red.spmv_blocks * (NR / KGroup<NR>::v)), dim3(256), 0, s,
+    AM_NR_SWITCH(nr, hipLaunchKernelGGL((k_spmv_p<NR, 32>), dim3(spmv_group_blocks<NR>(d) * (NR / KGroup<NR>::v)), dim3(256), 0, s,
                                         d.n, d.ell_w, d.ell_col, d.ell_val, d.z, po, pn, d.q,
                                         d.red.pd, d.m, d.red.pa, d.sc, d.shared, parity));
   }
