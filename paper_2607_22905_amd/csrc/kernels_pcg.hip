@@ -504,14 +504,18 @@ hipError_t launch_pcg_init(DeviceState& d, int nr, double tol, int maxit, int fl
 }
 
 // Workgroups per column group of the SpMV launch (and so its (p, Ap)
-// partials per column): the total stays at spmv_blocks whatever the number
-// of groups.  Every workgroup folds all the (r, z) partials of its group,
-// and every update workgroup all the (p, Ap) partials, so more workgroups
-// per group would only repeat that traffic; the sequence of dependent row
-// sweeps per SIMD is the same either way.
+// partials per column).  Every workgroup folds all the (r, z) partials of
+// its group, and every update workgroup all the (p, Ap) partials, so more
+// workgroups per group repeat that traffic.  With several groups the kernel
+// holds 224 VGPRs (two waves per SIMD, 512 resident workgroups), and a grid
+// of spmv_blocks / 2 in all keeps every workgroup resident: at 16 RHS on
+// 1M rows this measured 379 us against 406 (spmv_blocks in all), 417
+// (spmv_blocks / 4) and 482 (spmv_blocks per group).  One group keeps
+// spmv_blocks: halving it cost 71 -> 100 us at 128^3.
 template <int NR>
 static int spmv_group_blocks(const DeviceState& d) {
-  return std::max(1, d.red.spmv_blocks / (NR / KGroup<NR>::v));
+  constexpr int TR = NR / KGroup<NR>::v;
+  return std::max(1, d.red.spmv_blocks / (TR > 1 ? 2 * TR : 1));
 }
 
 static hipError_t update_xr(DeviceState& d, int nr, int parity, int init, hipStream_t s) {
