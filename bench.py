@@ -166,8 +166,9 @@ def main():
     per_step = np.diff(np.array([t0] + marks)) * 1e3
     its = max(i["iterations"] for i in infos[-1])
     # Kernel durations inside a solve: one more solve of the same system with
-    # every launch bracketed by HIP events on the library's stream (plain
-    # launches instead of the graph; same kernels, order, data and cache state).
+    # plain launches instead of the graph (same kernels, order, data and cache
+    # state), the first and last launch of each operation carrying HIP events
+    # on the library's stream (the dispatches' own start and end).
     if smooth is None:
         _, pinfo, prof = h.pcg_profile(b, P.tol, out=x)
         k_ms_total, k_launches = prof["local"]
@@ -235,7 +236,7 @@ def main():
                                 "k_localt on the smoothing blocks (block-Jacobi solves)"),
                      "avg_launch_us": k_ms * 1e3, "launches": k_launches,
                      "bytes_per_launch": k_bytes,
-                     "timing": ("HIP events around each launch of a profiled solve (plain launches)"
+                     "timing": ("HIP events attached to the launches of a profiled solve (plain launches, hipExtLaunchKernelGGL)"
                                 if smooth is None else "replayed alone (20 back-to-back launches)"),
                      "isolated_avg_launch_us": iso["local"] * 1e3},
         "other_kernels": others,

@@ -823,14 +823,20 @@ static hipError_t profiled_iteration(am_handle h, int nr, int parity, KernelProf
   int kinds[4];
   int nk = 0;
   hipError_t e;
+  // each operation's first and last launch carry the two events of its slot
+  // (the dispatches' own start and end); an operation that launched nothing
+  // gets them recorded in place (zero time)
   auto timed = [&](int kind, auto&& fn) -> hipError_t {
-    hipError_t r = hipEventRecord(h->evp[2 * nk], st);
+    d.prof_ev[0] = h->evp[2 * nk];
+    d.prof_ev[1] = h->evp[2 * nk + 1];
+    d.prof_used[0] = d.prof_used[1] = false;
+    hipError_t r = fn();
+    d.prof_ev[0] = d.prof_ev[1] = nullptr;
     if (r != hipSuccess) return r;
-    r = fn();
-    if (r != hipSuccess) return r;
-    r = hipEventRecord(h->evp[2 * nk + 1], st);
+    if (!d.prof_used[0] && (r = hipEventRecord(h->evp[2 * nk], st)) != hipSuccess) return r;
+    if (!d.prof_used[1] && (r = hipEventRecord(h->evp[2 * nk + 1], st)) != hipSuccess) return r;
     kinds[nk++] = kind;
-    return r;
+    return hipSuccess;
   };
   if ((e = timed(3, [&] { return launch_pcg_spmv(d, nr, parity, st); })) != hipSuccess) return e;
   if ((e = timed(4, [&] { return launch_pcg_update(d, nr, parity, st); })) != hipSuccess) return e;

@@ -6,8 +6,28 @@
 #include <cstdint>
 
 #include "am_device.h"
+#include <hip/hip_ext.h>
 
 namespace am {
+
+// Kernel launch that, in a profiled solve, attaches d.prof_ev[0] to the
+// first launch of an operation and d.prof_ev[1] to its last (the events
+// then hold the start and end of those dispatches, without the latency of a
+// separate event record).  Arguments are converted to the kernel's parameter
+// types, as the extended launch packs them as given.
+template <typename... KArgs, typename... Args>
+inline void am_launch(DeviceState& d, bool first, bool last, void (*kern)(KArgs...), dim3 grid,
+                      dim3 block, hipStream_t st, Args&&... args) {
+  static_assert(sizeof...(KArgs) == sizeof...(Args), "argument count");
+  hipEvent_t e0 = first ? d.prof_ev[0] : nullptr, e1 = last ? d.prof_ev[1] : nullptr;
+  if (e0 || e1) {
+    hipExtLaunchKernelGGL(kern, grid, block, 0, st, e0, e1, 0, static_cast<KArgs>(args)...);
+    if (e0) d.prof_used[0] = true;
+    if (e1) d.prof_used[1] = true;
+  } else {
+    hipLaunchKernelGGL(kern, grid, block, 0, st, static_cast<KArgs>(args)...);
+  }
+}
 
 typedef uint16_t bf16_t;
 

@@ -69,6 +69,10 @@ struct DeviceState {
   // count (slot log2 nrhs), -1 until tuned; the timed average per candidate
   int32_t tile_cand[5] = {-1, -1, -1, -1, -1};
   float tile_us[5][4] = {};
+  // profiled solves: events that the first and the last launch of the next
+  // operation carry (am_launch), and whether they were attached
+  hipEvent_t prof_ev[2] = {nullptr, nullptr};
+  bool prof_used[2] = {false, false};
 
   // device ordering and permuted matrix
   int32_t* dperm = nullptr;    // [n] device position -> original index

@@ -572,14 +572,14 @@ static void gemv_t(DeviceState& d, hipStream_t st, int pcg, int init) {
   const int nrb = (int)((d.NL + 63) / 64);
   const unsigned nw = (unsigned)std::max(1, nrb * d.op_parts);
   if constexpr (NR >= 4)
-    hipLaunchKernelGGL((k_iface_op_mfma<NR>), dim3((nw + 3) / 4), dim3(256), 0, st, (int)d.NL,
-                       d.ldS, d.Sinv, d.bpart, d.ypart, d.op_parts, pcg, init, d.shared);
+    am_launch(d, true, false, k_iface_op_mfma<NR>, dim3((nw + 3) / 4), dim3(256), st, (int)d.NL,
+              d.ldS, d.Sinv, d.bpart, d.ypart, d.op_parts, pcg, init, d.shared);
   else
-    hipLaunchKernelGGL((k_iface_op<NR>), dim3((nw + 3) / 4), dim3(256), 0, st, (int)d.NL, d.ldS,
-                       d.Sinv, d.bpart, d.ypart, d.op_parts, pcg, init, d.shared);
+    am_launch(d, true, false, k_iface_op<NR>, dim3((nw + 3) / 4), dim3(256), st, (int)d.NL, d.ldS,
+              d.Sinv, d.bpart, d.ypart, d.op_parts, pcg, init, d.shared);
   const unsigned nb = (unsigned)std::max<int64_t>(1, (d.NL * NR + 255) / 256);
-  hipLaunchKernelGGL((k_iface_reduce<NR>), dim3(nb), dim3(256), 0, st, (int)d.NL, d.ldS, d.ypart,
-                     d.op_parts, d.eta, pcg, init, d.red.pb, d.m, d.sc, d.shared);
+  am_launch(d, false, true, k_iface_reduce<NR>, dim3(nb), dim3(256), st, (int)d.NL, d.ldS, d.ypart,
+            d.op_parts, d.eta, pcg, init, d.red.pb, d.m, d.sc, d.shared);
 }
 
 hipError_t launch_iface_gemv(DeviceState& d, int nr, int pcg, int init, hipStream_t st) {

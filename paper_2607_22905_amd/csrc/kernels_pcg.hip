@@ -520,7 +520,7 @@ static int spmv_group_blocks(const DeviceState& d) {
 
 static hipError_t update_xr(DeviceState& d, int nr, int parity, int init, hipStream_t s) {
   const double* pn = d.p[1 - parity];
-  AM_NR_SWITCH(nr, hipLaunchKernelGGL(k_update_xr<NR>, dim3(d.m * (NR / KGroup<NR>::v)), dim3(256), 0, s, d.n, d.sub_ptr,
+  AM_NR_SWITCH(nr, am_launch(d, true, true, k_update_xr<NR>, dim3(d.m * (NR / KGroup<NR>::v)), dim3(256), s, d.n, d.sub_ptr,
                                       d.isub_ptr, d.mbf_off, d.mbf, d.bdst, pn, d.q, d.x, d.r,
                                       d.bpart, d.red.pa, spmv_group_blocks<NR>(d), d.red.pb, d.sc,
                                       d.shared, init, parity));
@@ -545,11 +545,11 @@ hipError_t launch_pcg_spmv(DeviceState& d, int nr, int parity, hipStream_t s) {
   const double* po = d.p[parity];
   double* pn = d.p[1 - parity];
   if (d.ell_w <= 8) {
-    AM_NR_SWITCH(nr, hipLaunchKernelGGL((k_spmv_p<NR, 8>), dim3(spmv_group_blocks<NR>(d) * (NR / KGroup<NR>::v)), dim3(256), 0, s,
+    AM_NR_SWITCH(nr, am_launch(d, true, true, k_spmv_p<NR, 8>, dim3(spmv_group_blocks<NR>(d) * (NR / KGroup<NR>::v)), dim3(256), s,
                                         d.n, d.ell_w, d.ell_col, d.ell_val, d.z, po, pn, d.q,
                                         d.red.pd, d.m, d.red.pa, d.sc, d.shared, parity));
   } else {
-    AM_NR_SWITCH(nr, hipLaunchKernelGGL((k_spmv_p<NR, 32>), dim3(spmv_group_blocks<NR>(d) * (NR / KGroup<NR>::v)), dim3(256), 0, s,
+    AM_NR_SWITCH(nr, am_launch(d, true, true, k_spmv_p<NR, 32>, dim3(spmv_group_blocks<NR>(d) * (NR / KGroup<NR>::v)), dim3(256), s,
                                         d.n, d.ell_w, d.ell_col, d.ell_val, d.z, po, pn, d.q,
                                         d.red.pd, d.m, d.red.pa, d.sc, d.shared, parity));
   }

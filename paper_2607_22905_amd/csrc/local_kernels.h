@@ -1342,15 +1342,21 @@ hipError_t localt_shape(DeviceState& d, const double* r, double* z, const double
                         int init, hipStream_t st) {
   using IT = typename AccT<FT>::T;
   unsigned off = 0;
+  int first_bk = -1, last_bk = -1;  // buckets launched first and last
+  for (int bk = 0; bk < 2; ++bk)
+    if (!d.bucket_sub[bk].empty()) {
+      if (first_bk < 0) first_bk = bk;
+      last_bk = bk;
+    }
   for (int bk = 0; bk < 2; ++bk) {
     const int nb = (int)d.bucket_sub[bk].size();
     if (!nb) continue;
     auto go = [&](auto kern, int threads) {
-      hipLaunchKernelGGL(kern, dim3(nb), dim3(threads), 0, st, d.d_bucket_sub[bk], d.sub_ptr,
-                         d.roff, d.fac_off, (const FT*)d.Lc, (const IT*)d.invd, r, z, mode,
-                         d.isub_ptr, d.isub_list, d.mbf_off, d.mbf, eta, d.q, d.red.pd, off,
-                         d.fuse_eta, d.Sinv, (int)d.NL, d.ldS, d.bpart, d.red.pb, d.m, init, d.sc,
-                         d.shared, d.n);
+      am_launch(d, bk == first_bk, bk == last_bk, kern, dim3(nb), dim3(threads), st,
+                d.d_bucket_sub[bk], d.sub_ptr, d.roff, d.fac_off, (const FT*)d.Lc,
+                (const IT*)d.invd, r, z, mode, d.isub_ptr, d.isub_list, d.mbf_off, d.mbf, eta,
+                d.q, d.red.pd, off, d.fuse_eta, d.Sinv, (int)d.NL, d.ldS, d.bpart, d.red.pb, d.m,
+                init, d.sc, d.shared, d.n);
     };
     if (bk == 0) {
       using S = TileAt<FT, 1, NT, I>;
@@ -1358,10 +1364,10 @@ hipError_t localt_shape(DeviceState& d, const double* r, double* z, const double
       if constexpr (NT == 16 && sizeof(FT) == 8) {
         if (!d.fuse_eta) {
           mf = true;
-          hipLaunchKernelGGL(k_localt_mf<16>, dim3(nb), dim3(256), 0, st, d.d_bucket_sub[bk], d.sub_ptr,
-                             d.roff, d.fac_off, (const double*)d.Lc, (const double*)d.invd, r, z,
-                             mode, d.isub_ptr, d.isub_list, d.mbf_off, d.mbf, eta, d.q, d.red.pd,
-                             off, d.shared, d.n);
+          am_launch(d, bk == first_bk, bk == last_bk, k_localt_mf<16>, dim3(nb), dim3(256), st,
+                    d.d_bucket_sub[bk], d.sub_ptr, d.roff, d.fac_off, (const double*)d.Lc,
+                    (const double*)d.invd, r, z, mode, d.isub_ptr, d.isub_list, d.mbf_off, d.mbf,
+                    eta, d.q, d.red.pd, off, d.shared, d.n);
         }
       }
       if (!mf) go(k_localt<FT, 1, NT, S::G, S::W>, 64 * S::G * S::W);
