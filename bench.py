@@ -56,6 +56,46 @@ def traffic_record(prec, config):
     return rec.get("hbm_bytes_per_launch")
 
 
+def gradient_timing(P, part, m, steps):
+    """Gradient evaluations of J = sum over observed cells of (p - p_obs)^2
+    with respect to ln K through the differentiation form: device TPFA
+    assembly, AlgMortar set-up, forward PCG, adjoint PCG on the same handle
+    and the face gradient, each evaluation timed whole (one warm-up first).
+    Observed cells and p_obs are those of the workload when it has them,
+    else 1000 seeded cells and p_obs = 0."""
+    import numpy as np
+    import torch
+
+    import paper_2607_22905_amd as am
+    dev = torch.device("cuda:0")
+    obs = P.extra.get("obs")
+    if obs is None:
+        obs = np.random.default_rng(7).choice(P.n, size=min(1000, P.n), replace=False)
+    obs_t = torch.as_tensor(np.asarray(obs, dtype=np.int64), device=dev)
+    pobs = torch.zeros(len(obs), dtype=torch.float64, device=dev)
+    atol = P.extra.get("adjoint_tol", 1e-12)
+    model = am.DarcyModel(P.faces, P.n, part, m, tol=P.tol, adjoint_tol=atol)
+    logK0 = torch.as_tensor(np.ascontiguousarray(P.logK), dtype=torch.float64, device=dev)
+    times = []
+    for i in range(steps + 1):
+        logK = logK0.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p = am.AlgMortarSolve.apply(logK, model)
+        J = ((p[obs_t] - pobs) ** 2).sum()
+        J.backward()
+        torch.cuda.synchronize()
+        if i > 0:
+            times.append((time.perf_counter() - t0) * 1e3)
+    fi, ai = model.last_info, getattr(model, "last_adjoint_info", {})
+    model.close()
+    return {"ms_per_gradient": float(np.median(times)), "evaluations": steps,
+            "forward_iterations": fi["iterations"] if fi else None,
+            "adjoint_iterations": ai.get("iterations") if ai else None,
+            "forward_tol": P.tol, "adjoint_tol": atol, "observed_cells": int(len(obs)),
+            "includes": "assembly, set-up, forward solve, adjoint solve, face gradient"}
+
+
 def cpu_baseline(P, part, iters, its_to_converge, smooth=None):
     """The FP64 oracle on the host cores: set-up (untimed for the metric),
     then a bounded sample of PCG iterations, extrapolated to a whole solve.
@@ -102,12 +142,16 @@ def main():
                     help="block-Jacobi steps before and after the AlgMortar correction (Sec. 5.4)")
     ap.add_argument("--smooth-blocks", default="8,8,32",
                     help="block sizes bx,by,bz of the smoothing partition (Cartesian workloads)")
+    ap.add_argument("--grad", type=int, default=0, metavar="K",
+                    help="also time K gradient evaluations of a least-squares loss on observed "
+                         "cells through the differentiation form (device assembly, set-up, "
+                         "forward solve, adjoint solve, face gradient); reported as 'gradient'")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding is described, not built.", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the solver has no multi-GPU sharding.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -242,12 +286,14 @@ def main():
         "other_kernels": others,
         "local_tile_autotune": {"choice": tile_choice, "candidate_us": tile_us},
     }
+    h.close()
+    if args.grad > 0:
+        out["gradient"] = gradient_timing(P, part, m, args.grad)
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(P, part, args.cpu_iters, its, smooth)
     else:
         out["cpu_baseline"] = None
-    h.close()
     print(json.dumps(out), flush=True)
 
 
