@@ -74,26 +74,34 @@ def gradient_timing(P, part, m, steps):
     obs_t = torch.as_tensor(np.asarray(obs, dtype=np.int64), device=dev)
     pobs = torch.zeros(len(obs), dtype=torch.float64, device=dev)
     atol = P.extra.get("adjoint_tol", 1e-12)
-    model = am.DarcyModel(P.faces, P.n, part, m, tol=P.tol, adjoint_tol=atol)
     logK0 = torch.as_tensor(np.ascontiguousarray(P.logK), dtype=torch.float64, device=dev)
-    times = []
-    for i in range(steps + 1):
-        logK = logK0.clone().requires_grad_(True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        p = am.AlgMortarSolve.apply(logK, model)
-        J = ((p[obs_t] - pobs) ** 2).sum()
-        J.backward()
-        torch.cuda.synchronize()
-        if i > 0:
-            times.append((time.perf_counter() - t0) * 1e3)
-    fi, ai = model.last_info, getattr(model, "last_adjoint_info", {})
-    model.close()
-    return {"ms_per_gradient": float(np.median(times)), "evaluations": steps,
-            "forward_iterations": fi["iterations"] if fi else None,
-            "adjoint_iterations": ai.get("iterations") if ai else None,
-            "forward_tol": P.tol, "adjoint_tol": atol, "observed_cells": int(len(obs)),
-            "includes": "assembly, set-up, forward solve, adjoint solve, face gradient"}
+    out = {}
+    for reuse in (True, False):
+        model = am.DarcyModel(P.faces, P.n, part, m, tol=P.tol, adjoint_tol=atol,
+                              reuse_handle=reuse)
+        times = []
+        for i in range(steps + 1):
+            # a new permeability each time (the handle's values must change)
+            logK = (logK0 * (1.0 + 0.01 * i)).requires_grad_(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            p = am.AlgMortarSolve.apply(logK, model)
+            J = ((p[obs_t] - pobs) ** 2).sum()
+            J.backward()
+            torch.cuda.synchronize()
+            if i > 0:
+                times.append((time.perf_counter() - t0) * 1e3)
+        fi, ai = model.last_info, getattr(model, "last_adjoint_info", {})
+        model.close()
+        out["ms_per_gradient" if reuse else "ms_per_gradient_new_handle"] = float(np.median(times))
+    out.update({"evaluations": steps,
+                "forward_iterations": fi["iterations"] if fi else None,
+                "adjoint_iterations": ai.get("iterations") if ai else None,
+                "forward_tol": P.tol, "adjoint_tol": atol, "observed_cells": int(len(obs)),
+                "includes": "assembly, set-up (numeric part on one reused handle; the whole "
+                            "set-up with a new handle per evaluation), forward solve, adjoint "
+                            "solve, face gradient"})
+    return out
 
 
 def cpu_baseline(P, part, iters, its_to_converge, smooth=None):

@@ -167,6 +167,29 @@ am_status am_structure(const am_csr* A, const int32_t* part, int32_t nparts, int
 am_status algmortar_setup(const am_csr* A, const int32_t* part, int32_t nparts,
                           const am_options* opt, void* stream, am_handle* out);
 
+/* New values for the matrix of an existing handle: Algorithm 1's numeric
+ * part (local operators and factors, MBFs, S and S^{-1}) is redone on the
+ * device, the structure, partition, local orderings and layout are kept
+ * (for a sequence of permeabilities on one grid, as in the differentiation
+ * form).  A: row_ptr and col_idx (host) must equal the set-up's; val holds
+ * the new values in the same order, host or device (values_on_device).  The
+ * values must pass the set-up's checks (finite, positive diagonal, bitwise
+ * symmetric, couplings not positive), and a coupling between two subdomains
+ * must be nonzero exactly where it was at set-up (the interfaces are kept).
+ * The factors, MBFs, S and S^{-1} equal, bit for bit, those of a handle set
+ * up from scratch on the new values with the same options (and so do its
+ * results, given the same wave layout of the local kernel: see
+ * algmortar_tile_choice).  The first call builds index maps of the
+ * pattern on the device (about 17 bytes per stored entry, kept until
+ * algmortar_destroy).  Synchronizes `stream` and the handle's work first.
+ * Errors: AM_ERR_ARG (pattern differs, non-finite value, a changed
+ * interface coupling), AM_ERR_NOT_SYMMETRIC, AM_ERR_POSITIVE_COUPLING,
+ * AM_ERR_NOT_SPD (diagonal, or a pivot of A_i or S), AM_ERR_UNSUPPORTED
+ * while a smoother is set, AM_ERR_HIP / AM_ERR_OOM.  When a check fails the
+ * handle keeps its previous values; when the factorization fails, apply, PCG
+ * and local solves return AM_ERR_NOT_SPD until an update succeeds. */
+am_status algmortar_update_values(am_handle h, const am_csr* A, void* stream);
+
 /* Block-Jacobi pre- and post-smoothing around the AlgMortar correction
  * (Sec. 5.4).  After this call algmortar_apply and algmortar_pcg use
  *   z = 0;  nu times z += B^{-1} (r - A z);  z += Mcal^{-1} (r - A z);
@@ -249,13 +272,20 @@ am_status algmortar_time_kernel(am_handle h, int32_t kernel, int32_t nrhs, int32
  * subdomains.  It runs, and synchronizes, on the first algmortar_apply or
  * algmortar_pcg with that count (or here).  choice: host (out), index of the
  * chosen candidate; ncand: host (out), number of candidates; us: host (out,
- * may be NULL), double[4], average launch time of each candidate in us. */
+ * may be NULL), double[4], average launch time of each candidate in us.
+ * The layouts add the waves' partial vectors in different orders, so two
+ * handles whose timings chose differently can differ in the last bits; with
+ * the environment variable ALGMORTAR_TILE=c, candidate c (clamped to the
+ * list) is used without timing (us then holds zeros), which makes results
+ * reproducible across handles and processes. */
 am_status algmortar_tile_choice(am_handle h, int32_t nrhs, int32_t* choice, int32_t* ncand,
                                 double* us);
 
 /* Measurement: algmortar_pcg with plain launches (no hipGraph), every launch
- * bracketed by HIP events on the handle's internal stream and the stop flag
- * read after each iteration, so the durations are those of the kernels inside
+ * timed with HIP events on the handle's internal stream (attached to the
+ * first and the last launch of each operation, hipExtLaunchKernelGGL, so
+ * they hold the dispatches' own start and end) and the stop flag read after
+ * each iteration, so the durations are those of the kernels inside
  * a real solve (same order, same data, same cache state).  Same arguments and
  * results as algmortar_pcg, plus kernel_ms[5] (host, out): summed launch
  * durations in ms, and launches[5] (host, out): launch counts, indexed by the

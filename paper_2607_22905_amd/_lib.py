@@ -57,6 +57,7 @@ _SIGS = {
     "algmortar_apply": [c_void_p, c_void_p, c_void_p, c_int32, c_int64, c_void_p],
     "algmortar_local_solve": [c_void_p, c_void_p, c_void_p, c_void_p],
     "algmortar_set_smoother": [c_void_p, c_void_p, c_int32, c_int32, c_void_p],
+    "algmortar_update_values": [c_void_p, POINTER(AmCsr), c_void_p],
     "algmortar_pcg": [c_void_p, c_void_p, c_void_p, c_int32, c_int64, c_double, c_int32, c_void_p, c_void_p],
     "algmortar_interfaces": [c_void_p] * 7,
     "algmortar_sizes": [c_void_p, POINTER(c_int64), POINTER(c_int64), POINTER(c_int64), POINTER(c_int64)],

@@ -22,10 +22,12 @@ class DarcyModel:
     faces: face list with arrays ``k, l, gk, gl, pD`` (``l = -1`` marks a
     Dirichlet face); n: cells; part/nparts: the partition; source: host
     float64[n] or None (``q``); tol / adjoint_tol: PCG tolerances of the
-    forward and adjoint solves."""
+    forward and adjoint solves; reuse_handle: keep one AlgMortar handle and
+    give it each new permeability's values (``update_values``: the numeric
+    set-up only) instead of setting up a new handle per solve."""
 
     def __init__(self, faces, n, part, nparts, source=None, tol=1e-10, adjoint_tol=1e-12,
-                 prec="fp64", maxit=10000, device=0):
+                 prec="fp64", maxit=10000, device=0, reuse_handle=False):
         import torch
         self.n = int(n)
         self.part = np.ascontiguousarray(part, dtype=np.int32)
@@ -41,6 +43,8 @@ class DarcyModel:
             self.source = torch.as_tensor(np.ascontiguousarray(source, dtype=np.float64),
                                           device=self.device)
         self.last_info = None
+        self.reuse_handle = bool(reuse_handle)
+        self._h = None
 
     def assemble(self, logK):
         """(matrix view for AlgMortar, right-hand side f + q) on the device."""
@@ -51,14 +55,24 @@ class DarcyModel:
 
     def forward_solve(self, logK):
         """(p, handle): the handle keeps the factored preconditioner for the
-        adjoint solve; the caller closes it."""
+        adjoint solve; the caller closes it, unless the model reuses its
+        handle (then ``close`` of the model does)."""
         A, f = self.assemble(logK)
-        h = AlgMortar(A, self.part, self.nparts, prec=self.prec)
+        if self.reuse_handle and self._h is not None:
+            self._h.update_values(A)
+            h = self._h
+        else:
+            h = AlgMortar(A, self.part, self.nparts, prec=self.prec)
+            if self.reuse_handle:
+                self._h = h
         p, info, _ = h.pcg(f, self.tol, maxit=self.maxit)
         self.last_info = info[0]
         return p, h
 
     def close(self):
+        if self._h is not None:
+            self._h.close()
+            self._h = None
         self.tpfa.close()
 
 
@@ -97,7 +111,8 @@ def _make_function():
                                             tol=model.adjoint_tol, maxit=model.maxit)
                 model.last_adjoint_info = info
             finally:
-                h.close()
+                if not model.reuse_handle:
+                    h.close()
                 ctx.handle = None
             return g, None
 

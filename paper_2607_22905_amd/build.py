@@ -22,6 +22,7 @@ SOURCES = [
     "host_structure.cpp",
     "algmortar_api.cpp",
     "kernels_local.hip",
+    "kernels_values.hip",
     "kernels_local_f64.hip",
     "kernels_local_f32.hip",
     "kernels_local_bf16.hip",

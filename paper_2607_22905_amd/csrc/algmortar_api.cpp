@@ -36,6 +36,13 @@ struct am_handle_s {
   am_handle bj = nullptr;
   SmoothDevice sm;
   std::vector<void*> sm_allocs;
+  // the set-up's CSR pattern (checked by algmortar_update_values), the maps
+  // of that entry point, and whether the numeric set-up is valid (false
+  // after an update whose factorization failed)
+  std::vector<int64_t> pat_rp;
+  std::vector<int32_t> pat_ci;
+  ValueMaps vm;
+  bool numeric_ok = true;
 };
 
 struct am_tpfa_s {
@@ -196,6 +203,7 @@ am_status algmortar_destroy(am_handle h) {
   if (h->bj) algmortar_destroy(h->bj);
   if (h->d.graph) hipGraphExecDestroy(h->d.graph);
   for (void* p : h->d.allocs) hipFree(p);
+  for (void* p : h->vm.allocs) hipFree(p);
   if (h->d.h_flags) hipHostFree(h->d.h_flags);
   if (h->ev0) hipEventDestroy(h->ev0);
   if (h->ev1) hipEventDestroy(h->ev1);
@@ -256,6 +264,10 @@ static am_status setup_impl(const am_csr* A, const int32_t* part, int32_t nparts
   if ((s = validate_csr(H, e)) != AM_OK) { fail(h, s, e); return bail(s); }
   if ((s = validate_partition(H.n, part, nparts, e)) != AM_OK) { fail(h, s, e); return bail(s); }
   mark("validation", nullptr);
+  if (!plain) {
+    h->pat_rp.assign(H.rp, H.rp + H.n + 1);
+    h->pat_ci.assign(H.ci, H.ci + H.nnz);
+  }
   Structure& st = h->st;
   LocalPlan& lp = h->lp;
   if ((s = build_structure(H, part, nparts, opt.mortar, st, e)) != AM_OK) { fail(h, s, e); return bail(s); }
@@ -585,6 +597,8 @@ static am_status check_vec_args(am_handle h, const void* a, const void* b, int32
                                 int64_t ld) {
   if (!h) return fail(nullptr, AM_ERR_ARG, "null handle");
   if (!a || !b) return fail(h, AM_ERR_ARG, "null vector");
+  if (!h->numeric_ok)
+    return fail(h, AM_ERR_NOT_SPD, "the last algmortar_update_values failed: no preconditioner");
   if (nrhs < 1 || pow2_at_least(nrhs) > h->d.max_nrhs)
     return fail(h, AM_ERR_ARG, "nrhs out of range (max_nrhs at set-up)");
   if (nrhs > 1 && ld < h->d.n) return fail(h, AM_ERR_ARG, "ld < n");
@@ -601,6 +615,15 @@ static am_status autotune_tiles(am_handle h, int nr) {
   const int slot = tile_slot(nr);
   if (d.tile_cand[slot] >= 0) return AM_OK;
   const int nc = tile_candidates(nr);
+  // ALGMORTAR_TILE=c pins candidate c (clamped to the list): the layouts
+  // sum the waves' partial vectors in different orders, so results of
+  // handles (or processes) whose timings chose differently can differ in
+  // the last bits; a pinned layout makes them reproducible
+  if (const char* env = std::getenv("ALGMORTAR_TILE")) {
+    const int c = std::atoi(env);
+    d.tile_cand[slot] = std::min(std::max(c, 0), nc - 1);
+    return AM_OK;
+  }
   hipStream_t st = h->own;
   HCHK(launch_fill(d.r, d.n * nr, 0.0, st));
   HCHK(launch_fill(d.z, d.n * nr, 0.0, st));
@@ -651,6 +674,198 @@ static void drop_smoother(am_handle h) {
   if (h->bj) algmortar_destroy(h->bj);
   h->bj = nullptr;
   h->sm = SmoothDevice{};
+}
+
+// ---------------------------------------------------------------------------
+// New values on an existing handle.  The maps below are built from the
+// set-up's pattern, partition and layout at the first update; they place each
+// caller entry where the set-up put its value, in the set-up's order.
+static am_status build_value_maps(am_handle h) {
+  ValueMaps& vm = h->vm;
+  DeviceState& d = h->d;
+  const Structure& st = h->st;
+  const LocalPlan& lp = h->lp;
+  const int64_t n = d.n, nnz = (int64_t)h->pat_ci.size();
+  const int64_t* rp = h->pat_rp.data();
+  const int32_t* ci = h->pat_ci.data();
+  auto find = [&](int64_t row, int32_t col) -> int64_t {
+    const int32_t* b = ci + rp[row];
+    const int32_t* e = ci + rp[row + 1];
+    const int32_t* it = std::lower_bound(b, e, col);
+    return (it == e || *it != col) ? -1 : rp[row] + (it - b);
+  };
+  // device-order rows with ascending device columns, as the set-up builds them
+  std::vector<int64_t> prp(n + 1, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t o = lp.dperm[i];
+    prp[i + 1] = prp[i] + (rp[o + 1] - rp[o]);
+  }
+  std::vector<int64_t> vpos((size_t)nnz);
+  parallel_for((n + 1023) / 1024, 1, [&](int64_t c) {
+    std::vector<std::pair<int32_t, int64_t>> row;
+    const int64_t hi = std::min<int64_t>(n, (c + 1) * 1024);
+    for (int64_t i = c * 1024; i < hi; ++i) {
+      const int64_t o = lp.dperm[i];
+      row.clear();
+      for (int64_t p = rp[o]; p < rp[o + 1]; ++p) row.emplace_back(lp.dpos[ci[p]], p);
+      std::sort(row.begin(), row.end());
+      for (size_t t = 0; t < row.size(); ++t) vpos[prp[i] + t] = row[t].second;
+    }
+  });
+  vm.code_h.assign((size_t)nnz, 0);
+  vm.cross_h.assign((size_t)nnz, 0);
+  parallel_for((n + 4095) / 4096, 1, [&](int64_t c) {
+    const int64_t hi = std::min<int64_t>(n, (c + 1) * 4096);
+    for (int64_t k = c * 4096; k < hi; ++k)
+      for (int64_t p = rp[k]; p < rp[k + 1]; ++p) {
+        const int32_t col = ci[p];
+        vm.code_h[p] = col == k ? -2 : find(col, (int32_t)k);
+        if (st.part[col] != st.part[k]) vm.cross_h[p] = 2;
+      }
+  });
+  std::vector<int64_t> epos((size_t)d.NE);
+  for (int64_t e = 0; e < d.NE; ++e) {
+    const int64_t p = find(st.edge_k[e], st.edge_l[e]);
+    if (p < 0) return fail(h, AM_ERR_ARG, "internal: an interface edge is not in the pattern");
+    epos[e] = p;
+    vm.cross_h[p] = 1;
+    if (vm.code_h[p] >= 0) vm.cross_h[vm.code_h[p]] = 1;
+  }
+  // boundary-weight entries: per (interface, side) slot, the edges grouped by
+  // local row after a stable sort, summed in that order
+  const int64_t NL = d.NL, npair = 2 * NL;
+  std::vector<int64_t> bidx((size_t)npair);
+  for (int32_t s2 = 0; s2 < st.m; ++s2)
+    for (int64_t pi = st.isub_ptr[s2]; pi < st.isub_ptr[s2 + 1]; ++pi) {
+      const int32_t nidx = st.isub_list[pi];
+      bidx[2 * nidx + (st.iface_ij[2 * nidx] == s2 ? 0 : 1)] = pi;
+    }
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> wts((size_t)npair);
+  for (int64_t nidx = 0; nidx < NL; ++nidx) {
+    const int32_t i = st.iface_ij[2 * nidx], j = st.iface_ij[2 * nidx + 1];
+    for (int64_t e2 = st.iface_ptr[nidx]; e2 < st.iface_ptr[nidx + 1]; ++e2) {
+      wts[bidx[2 * nidx]].emplace_back(lp.dpos[st.edge_k[e2]] - (int32_t)st.sub_ptr[i], (int32_t)e2);
+      wts[bidx[2 * nidx + 1]].emplace_back(lp.dpos[st.edge_l[e2]] - (int32_t)st.sub_ptr[j], (int32_t)e2);
+    }
+  }
+  std::vector<int64_t> bw_ptr(1, 0);
+  std::vector<int32_t> bw_src;
+  for (int64_t pi = 0; pi < npair; ++pi) {
+    auto& v = wts[pi];
+    std::stable_sort(v.begin(), v.end(),
+                     [](const std::pair<int32_t, int32_t>& a, const std::pair<int32_t, int32_t>& b) {
+                       return a.first < b.first;
+                     });
+    for (size_t t = 0; t < v.size(); ++t) {
+      if (t == 0 || v[t].first != v[t - 1].first) bw_ptr.push_back(bw_ptr.back());
+      bw_src.push_back(v[t].second);
+      bw_ptr.back() += 1;
+    }
+  }
+  vm.nnz = nnz;
+  vm.nbw = (int64_t)bw_ptr.size() - 1;
+  hipStream_t st0 = h->own;
+  HCHK(upload(vm.allocs, &vm.vpos, vpos, st0));
+  HCHK(upload(vm.allocs, &vm.code, vm.code_h, st0));
+  HCHK(upload(vm.allocs, &vm.cross, vm.cross_h, st0));
+  HCHK(upload(vm.allocs, &vm.epos, epos, st0));
+  HCHK(upload(vm.allocs, &vm.bw_ptr, bw_ptr, st0));
+  HCHK(upload(vm.allocs, &vm.bw_src, bw_src, st0));
+  HCHK(dalloc(vm.allocs, &vm.vals, (size_t)nnz));
+  HCHK(dalloc(vm.allocs, &vm.bad, 1));
+  vm.built = true;
+  return AM_OK;
+}
+
+am_status algmortar_update_values(am_handle h, const am_csr* A, void* stream) {
+  if (!h) return fail(nullptr, AM_ERR_ARG, "null handle");
+  if (!A || !A->row_ptr || !A->col_idx || !A->val) return fail(h, AM_ERR_ARG, "A: null pointer");
+  if (h->pat_rp.empty()) return fail(h, AM_ERR_ARG, "the handle keeps no pattern");
+  if (h->bj)
+    return fail(h, AM_ERR_UNSUPPORTED, "remove the smoother (steps 0) before setting new values");
+  const int64_t nnz = (int64_t)h->pat_ci.size();
+  if (A->n != h->d.n || A->nnz != nnz ||
+      std::memcmp(A->row_ptr, h->pat_rp.data(), sizeof(int64_t) * (size_t)(A->n + 1)) != 0 ||
+      std::memcmp(A->col_idx, h->pat_ci.data(), sizeof(int32_t) * (size_t)nnz) != 0)
+    return fail(h, AM_ERR_ARG, "A's pattern differs from the one the handle was set up with");
+  DeviceState& d = h->d;
+  HCHK(hipSetDevice(d.device));
+  if (stream) HCHK(hipStreamSynchronize((hipStream_t)stream));
+  hipStream_t st = h->own;
+  HCHK(hipStreamSynchronize(st));
+  if (!h->vm.built) {
+    am_status s = build_value_maps(h);
+    if (s != AM_OK) return s;
+  }
+  ValueMaps& vm = h->vm;
+  const double* v = A->val;
+  if (!A->values_on_device) {
+    HCHK(hipMemcpyAsync(vm.vals, A->val, sizeof(double) * (size_t)nnz, hipMemcpyHostToDevice, st));
+    v = vm.vals;
+  }
+  // the set-up's checks; the handle is unchanged when they fail
+  HCHK(launch_check_values(vm, v, st));
+  unsigned long long bad = 0;
+  HCHK(hipMemcpyAsync(&bad, vm.bad, sizeof(bad), hipMemcpyDeviceToHost, st));
+  HCHK(hipStreamSynchronize(st));
+  if (bad != ~0ull) {
+    const int64_t p = (int64_t)bad, t = vm.code_h[p];
+    double a = 0.0, b = 0.0;
+    HCHK(hipMemcpy(&a, v + p, sizeof(double), hipMemcpyDefault));
+    if (t >= 0) HCHK(hipMemcpy(&b, v + t, sizeof(double), hipMemcpyDefault));
+    const int64_t k = (int64_t)(std::upper_bound(h->pat_rp.begin(), h->pat_rp.end(), p) - h->pat_rp.begin()) - 1;
+    const std::string at = "(" + std::to_string(k) + "," + std::to_string(h->pat_ci[p]) + ")";
+    if (!std::isfinite(a)) return fail(h, AM_ERR_ARG, "A: non-finite value at " + at);
+    if (t == -2) return fail(h, AM_ERR_NOT_SPD, "A: nonpositive diagonal at " + at);
+    if (std::memcmp(&a, &b, sizeof(double)) != 0 && !(a == 0.0 && b == 0.0))
+      return fail(h, AM_ERR_NOT_SYMMETRIC, "A not symmetric at " + at);
+    if (a > 0) return fail(h, AM_ERR_POSITIVE_COUPLING, "positive off-diagonal at " + at);
+    return fail(h, AM_ERR_ARG, "A: the nonzero couplings between subdomains must stay those of the "
+                               "set-up (entry " + at + ")");
+  }
+  // Algorithm 1's numeric part on the new values
+  h->numeric_ok = false;
+  HCHK(launch_place_values(d, vm, v, st));
+  const size_t esz = d.prec == AM_FP64 ? 8 : (d.prec == AM_FP32 ? 4 : 2);
+  const size_t nfac = (size_t)h->lp.fac_off[h->st.m];
+  void* Lr = nullptr;
+  HCHK(hipMalloc(&Lr, nfac * esz));
+  d.Lr = Lr;
+  hipError_t he = hipMemsetAsync(d.Lc, 0, nfac * esz, st);
+  if (he == hipSuccess) he = hipMemsetAsync(Lr, 0, nfac * esz, st);
+  if (he == hipSuccess) he = hipMemsetAsync(d.fail, 0xFF, 4 * sizeof(int32_t), st);
+  if (he == hipSuccess) he = launch_band_factor(d, st);
+  if (he == hipSuccess) he = launch_mbf(d, st);
+  if (he == hipSuccess) he = launch_invert_diag(d, st);
+  if (he == hipSuccess) he = launch_assemble_S(d, st);
+  if (he == hipSuccess && d.NL > 0) {
+    const size_t nS = (size_t)d.ldS * d.ldS;
+    const int64_t ptiles = trtri_part_tiles(d.ldS / 64);
+    double *L = nullptr, *Li = nullptr, *part = nullptr;
+    he = hipMalloc((void**)&L, nS * sizeof(double));
+    if (he == hipSuccess) he = hipMalloc((void**)&Li, nS * sizeof(double));
+    if (he == hipSuccess && ptiles > 0) he = hipMalloc((void**)&part, (size_t)ptiles * 4096 * sizeof(double));
+    if (he == hipSuccess) he = dense_cholesky_inverse(d, L, Li, part, st);
+    const hipError_t he2 = hipStreamSynchronize(st);
+    if (he == hipSuccess) he = he2;
+    hipFree(L);
+    hipFree(Li);
+    hipFree(part);
+  }
+  const hipError_t he3 = hipStreamSynchronize(st);
+  if (he == hipSuccess) he = he3;
+  hipFree(Lr);
+  d.Lr = nullptr;
+  HCHK(he);
+  int32_t fl[4];
+  HCHK(hipMemcpy(fl, d.fail, sizeof(fl), hipMemcpyDeviceToHost));
+  if (fl[0] >= 0)
+    return fail(h, AM_ERR_NOT_SPD, "A_i not SPD: subdomain " + std::to_string(fl[0]) + " pivot " +
+                                       std::to_string(fl[1]));
+  if (fl[2] >= 0)
+    return fail(h, AM_ERR_NOT_SPD, "interface matrix S not SPD at row " + std::to_string(fl[2]));
+  h->numeric_ok = true;
+  return AM_OK;
 }
 
 am_status algmortar_set_smoother(am_handle h, const int32_t* blocks, int32_t nblocks,

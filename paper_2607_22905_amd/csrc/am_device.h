@@ -183,6 +183,29 @@ hipError_t launch_pcg_rr0(DeviceState& d, int nrhs, hipStream_t s);  // ||r_0||^
 // the stop test on the ||r||^2 partials of the last update (kernels_local.hip)
 hipError_t launch_stop_test(DeviceState& d, int nrhs, int init, hipStream_t s);
 
+// ---- new values on an existing handle (kernels_values.hip) ----
+// Index maps from the caller's CSR order (built at the first update; owned
+// by the handle through `allocs`).
+struct ValueMaps {
+  bool built = false;
+  int64_t nnz = 0, nbw = 0;
+  int64_t* vpos = nullptr;   // [nnz] caller position of device-order CSR entry q
+  int64_t* code = nullptr;   // [nnz] -2 diagonal, -1 no transpose, else transpose position
+  int8_t* cross = nullptr;   // [nnz] 0 inside a subdomain, 1 interface edge, 2 zero between subdomains
+  int64_t* epos = nullptr;   // [NE] caller position of interface edge e
+  int64_t* bw_ptr = nullptr; // [nbw + 1] edges of boundary-weight entry t ..
+  int32_t* bw_src = nullptr; // [2 NE] .. in the set-up's summation order
+  double* vals = nullptr;    // [nnz] device copy of host-resident new values
+  unsigned long long* bad = nullptr;  // lowest failing position of the checks
+  std::vector<int64_t> code_h;  // host copies of code and cross (error messages)
+  std::vector<int8_t> cross_h;
+  std::vector<void*> allocs;
+};
+// *vm.bad = lowest position of v that fails the set-up's checks (else ~0)
+hipError_t launch_check_values(const ValueMaps& vm, const double* v, hipStream_t s);
+// d.pv, d.ell_val, d.e_a and d.bw_val from v
+hipError_t launch_place_values(DeviceState& d, const ValueMaps& vm, const double* v, hipStream_t s);
+
 // ---- block-Jacobi smoothing (kernels_smooth.hip) ----
 struct SmoothDevice {
   DeviceState* bj = nullptr;        // band factors of the plain diagonal blocks

@@ -144,6 +144,13 @@ class AlgMortar:
         except Exception:
             pass
 
+    def update_values(self, A, stream=None):
+        """New values for the matrix (same pattern as at set-up; ``A.val`` on
+        the host or a float64 CUDA tensor): Algorithm 1's numeric part is
+        redone, the structure and layout are kept."""
+        s, keep = _csr(A)
+        check(load().algmortar_update_values(self._h, byref(s), _stream(stream)), self._h)
+
     def set_smoother(self, blocks, nblocks, steps, stream=None):
         """Block-Jacobi pre/post smoothing (Sec. 5.4) on the blocks of the
         host partition ``blocks`` (int32[n]), ``steps`` before and after the
