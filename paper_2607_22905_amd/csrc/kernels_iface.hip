@@ -143,57 +143,98 @@ __device__ __forceinline__ void mf_each(const MfAcc& acc, F&& f) {
     for (int v = 0; v < 4; ++v) f(16 * w + lk + 4 * v, 16 * t + li, acc.t[t][v]);
 }
 
-// Cholesky of the diagonal tile (b, b), in place (lower; upper zeroed).
+// Cholesky of the diagonal tile (b, b), in place (lower; upper zeroed), by
+// symmetric elimination on unscaled columns: step k takes the pivot
+// d_k = a_kk and updates a_ij -= a_ik (a_jk / d_k) for k < j <= i.  Thread
+// (column j = tid % 64, rows tid / 64 + 4 u) keeps its 16 entries in
+// registers for the whole factorization; the owners of column k + 1 publish
+// it (after their step-k update) to one of two LDS column buffers, so each
+// step is one barrier.  At the end l_jj = sqrt(d_j) and l_ij = a_ij / l_jj.
+// A pivot <= 0 is recorded in fail (and taken as 1).
 __global__ __launch_bounds__(256) void k_potrf_diag(double* A, int ld, int b, int32_t* fail) {
-  __shared__ Tile T;
+  __shared__ double col[2][64];
+  __shared__ double sq[64];
+  const int tid = threadIdx.x, jj = tid & 63, r0 = tid >> 6;
   double* p = A + (size_t)b * 64 * ld + (size_t)b * 64;
-  load_tile(T, p, ld, false);
+  double v[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) v[u] = p[(size_t)(r0 + 4 * u) * ld + jj];
+  if (jj == 0)
+#pragma unroll
+    for (int u = 0; u < 16; ++u) col[0][r0 + 4 * u] = v[u];
   __syncthreads();
-  const int tid = threadIdx.x;
   for (int k = 0; k < 64; ++k) {
-    const double d = T[k][k];
-    const bool bad = !(d > 0.0);
-    const double ljj = bad ? 1.0 : sqrt(d);
-    __syncthreads();
-    if (tid == 0) {
-      T[k][k] = ljj;
-      if (bad && atomicCAS(fail, -1, b * 64 + k) == -1) fail[1] = b * 64 + k;
+    const double* ck = col[k & 1];
+    double d = ck[k];
+    if (!(d > 0.0)) {
+      d = 1.0;
+      if (tid == 0 && atomicCAS(fail, -1, b * 64 + k) == -1) fail[1] = b * 64 + k;
     }
-    if (tid > k && tid < 64) T[tid][k] /= ljj;
-    __syncthreads();
-    for (int t = tid; t < 4096; t += blockDim.x) {
-      const int i = t >> 6, jj = t & 63;
-      if (jj > k && jj <= i) T[i][jj] -= T[i][k] * T[jj][k];
-    }
+    if (tid == 0) sq[k] = sqrt(d);
+    const double ajk = ck[jj] * (1.0 / d);  // a_jk / d_k for this thread's column
+    if (jj > k)
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int i = r0 + 4 * u;
+        if (i >= jj) v[u] -= ck[i] * ajk;
+      }
+    if (jj == k + 1)
+#pragma unroll
+      for (int u = 0; u < 16; ++u) col[(k + 1) & 1][r0 + 4 * u] = v[u];
     __syncthreads();
   }
-  for (int t = tid; t < 4096; t += blockDim.x) {
-    const int r = t >> 6, c = t & 63;
-    p[(size_t)r * ld + c] = c <= r ? T[r][c] : 0.0;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int i = r0 + 4 * u;
+    p[(size_t)i * ld + jj] = jj < i ? v[u] / sq[jj] : (jj == i ? sq[jj] : 0.0);
   }
 }
 
-// Panel: A_ib <- A_ib L_bb^{-T} for i = b+1.. (one tile per block, one row per thread).
-__global__ __launch_bounds__(64) void k_trsm_panel(double* A, int ld, int b) {
+// Panel: A_ib <- A_ib L_bb^{-T} for i = b+1.. (one tile per workgroup):
+// X L^T = A by columns, x_j = (a_j - sum_{c < j} x_c l_jc) (1 / l_jj) with
+// the terms in increasing c.  Thread (column j = tid % 64, rows tid / 64 + 4 u)
+// keeps its 16 entries in registers; finished column c goes to one of two
+// LDS buffers for the others, so each step is one barrier.
+__global__ __launch_bounds__(256) void k_trsm_panel(double* A, int ld, int b) {
   __shared__ Tile L;
-  __shared__ Tile X;
+  __shared__ double col[2][64];
   const int i = b + 1 + blockIdx.x;
+  const int tid = threadIdx.x, jj = tid & 63, r0 = tid >> 6;
   const double* pl = A + (size_t)b * 64 * ld + (size_t)b * 64;
   double* pa = A + (size_t)i * 64 * ld + (size_t)b * 64;
-  load_tile(L, pl, ld, false);
-  load_tile(X, pa, ld, false);
-  __syncthreads();
-  const int r = threadIdx.x;
-  for (int c = 0; c < 64; ++c) {
-    double v = X[r][c];
-    for (int k = 0; k < c; ++k) v -= X[r][k] * L[c][k];
-    X[r][c] = v / L[c][c];
+  {
+    TileRegs rl;
+    tile_fetch(rl, pl, ld);
+    tile_put(L, rl, false);
   }
+  double v[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) v[u] = pa[(size_t)(r0 + 4 * u) * ld + jj];
   __syncthreads();
-  for (int t = threadIdx.x; t < 4096; t += blockDim.x) {
-    const int rr = t >> 6, c = t & 63;
-    pa[(size_t)rr * ld + c] = X[rr][c];
+  const double rjj = 1.0 / L[jj][jj];
+  if (jj == 0)
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      v[u] *= rjj;
+      col[0][r0 + 4 * u] = v[u];
+    }
+  __syncthreads();
+  for (int c = 0; c < 63; ++c) {
+    const double* xc = col[c & 1];
+    const double ljc = L[jj][c];
+    if (jj > c)
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v[u] -= xc[r0 + 4 * u] * ljc;
+    if (jj == c + 1)
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        v[u] *= rjj;
+        col[(c + 1) & 1][r0 + 4 * u] = v[u];
+      }
+    __syncthreads();
   }
+#pragma unroll
+  for (int u = 0; u < 16; ++u) pa[(size_t)(r0 + 4 * u) * ld + jj] = v[u];
 }
 
 // Trailing update A_ij -= A_ib A_jb^T for b < j <= i.
@@ -549,7 +590,7 @@ hipError_t dense_cholesky_inverse(DeviceState& d, double* L, double* Li, double*
   for (int b = 0; b < T; ++b) {
     hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, st, L, ld, b, d.fail + 2);
     if (b + 1 < T) {
-      hipLaunchKernelGGL(k_trsm_panel, dim3(T - b - 1), dim3(64), 0, st, L, ld, b);
+      hipLaunchKernelGGL(k_trsm_panel, dim3(T - b - 1), dim3(256), 0, st, L, ld, b);
       hipLaunchKernelGGL(k_syrk_update, dim3(T - b - 1, T - b - 1), dim3(256), 0, st, L, ld, b);
     }
   }
