@@ -281,6 +281,34 @@ __global__ __launch_bounds__(64) void k_trtri_diag(const double* L, double* Li, 
   }
 }
 
+// Trailing update with two panels, A_ij -= A_ib A_jb^T + A_i,b+1 A_j,b+1^T
+// for b+2 <= j <= i: one read-modify-write of the output tile for two
+// panels (the second pair of tiles is fetched while the first is multiplied).
+__global__ __launch_bounds__(256) void k_syrk_update2(double* A, int ld, int b) {
+  const int j = b + 2 + blockIdx.x, i = b + 2 + blockIdx.y;
+  if (j > i) return;
+  __shared__ Tile Ai;
+  __shared__ Tile Bj;
+  TileRegs ra, rb;
+  tile_fetch(ra, A + (size_t)i * 64 * ld + (size_t)b * 64, ld);
+  tile_fetch(rb, A + (size_t)j * 64 * ld + (size_t)b * 64, ld);
+  tile_put(Ai, ra, false);
+  tile_put(Bj, rb, true);
+  __syncthreads();
+  tile_fetch(ra, A + (size_t)i * 64 * ld + (size_t)(b + 1) * 64, ld);
+  tile_fetch(rb, A + (size_t)j * 64 * ld + (size_t)(b + 1) * 64, ld);
+  MfAcc acc;
+  mf_zero(acc);
+  mf_mac(acc, Ai, Bj);
+  __syncthreads();
+  tile_put(Ai, ra, false);
+  tile_put(Bj, rb, true);
+  __syncthreads();
+  mf_mac(acc, Ai, Bj);
+  double* pc = A + (size_t)i * 64 * ld + (size_t)j * 64;
+  mf_each(acc, [&](int r, int c, double v) { pc[(size_t)r * ld + c] -= v; });
+}
+
 // Off-diagonal tiles of L^{-1} at distance d: Li_ij = -Li_ii sum_{k=j}^{i-1} L_ik Li_kj.
 __global__ __launch_bounds__(256) void k_trtri_off(const double* L, double* Li, int ld, int d) {
   const int i = d + blockIdx.x, j = blockIdx.x;
@@ -587,12 +615,23 @@ hipError_t dense_cholesky_inverse(DeviceState& d, double* L, double* Li, double*
   if (e != hipSuccess) return e;
   e = hipMemsetAsync(Li, 0, sizeof(double) * (size_t)ld * ld, st);
   if (e != hipSuccess) return e;
-  for (int b = 0; b < T; ++b) {
+  // right-looking tiled Cholesky with a look-ahead of one panel: after panel
+  // b, only column b+1 is updated; panel b+1 is factored; then panels b and
+  // b+1 update the rest of the trailing matrix together
+  for (int b = 0; b < T;) {
     hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, st, L, ld, b, d.fail + 2);
-    if (b + 1 < T) {
-      hipLaunchKernelGGL(k_trsm_panel, dim3(T - b - 1), dim3(256), 0, st, L, ld, b);
-      hipLaunchKernelGGL(k_syrk_update, dim3(T - b - 1, T - b - 1), dim3(256), 0, st, L, ld, b);
+    if (b + 1 == T) break;
+    hipLaunchKernelGGL(k_trsm_panel, dim3(T - b - 1), dim3(256), 0, st, L, ld, b);
+    if (b + 2 == T) {  // one tile left
+      hipLaunchKernelGGL(k_syrk_update, dim3(1, 1), dim3(256), 0, st, L, ld, b);
+      b += 1;
+      continue;
     }
+    hipLaunchKernelGGL(k_syrk_update, dim3(1, T - b - 1), dim3(256), 0, st, L, ld, b);
+    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, st, L, ld, b + 1, d.fail + 2);
+    hipLaunchKernelGGL(k_trsm_panel, dim3(T - b - 2), dim3(256), 0, st, L, ld, b + 1);
+    hipLaunchKernelGGL(k_syrk_update2, dim3(T - b - 2, T - b - 2), dim3(256), 0, st, L, ld, b);
+    b += 2;
   }
   hipLaunchKernelGGL(k_trtri_diag, dim3(T), dim3(64), 0, st, L, Li, ld);
   for (int dd = 1; dd < T; ++dd) {
