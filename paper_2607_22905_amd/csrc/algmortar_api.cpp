@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -81,13 +82,29 @@ hipError_t dalloc(std::vector<void*>& allocs, T** p, size_t count) {
 }
 
 template <class T>
-hipError_t upload(std::vector<void*>& allocs, T** p, const std::vector<T>& v, hipStream_t s) {
-  hipError_t e = dalloc(allocs, p, v.size());
-  if (e != hipSuccess || v.empty()) return e;
-  e = hipMemcpyAsync(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+hipError_t upload(std::vector<void*>& allocs, T** p, const T* v, size_t count, hipStream_t s) {
+  hipError_t e = dalloc(allocs, p, count);
+  if (e != hipSuccess || count == 0) return e;
+  e = hipMemcpyAsync(*p, v, count * sizeof(T), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return e;
   return hipStreamSynchronize(s);
 }
+
+template <class T>
+hipError_t upload(std::vector<void*>& allocs, T** p, const std::vector<T>& v, hipStream_t s) {
+  return upload(allocs, p, v.data(), v.size(), s);
+}
+
+// host array without the zero fill of std::vector (for large arrays that a
+// parallel loop writes in full)
+template <class T>
+struct HostBuf {
+  std::unique_ptr<T[]> p;
+  size_t n = 0;
+  explicit HostBuf(size_t m) : p(new T[m]), n(m) {}
+  T& operator[](size_t i) { return p[i]; }
+  const T& operator[](size_t i) const { return p[i]; }
+};
 
 int pow2_at_least(int x) {
   int r = 1;
@@ -339,8 +356,8 @@ static am_status setup_impl(const am_csr* A, const int32_t* part, int32_t nparts
   const std::vector<int32_t>& dperm = lp.dperm;
   const std::vector<int32_t>& dpos = lp.dpos;
   std::vector<int64_t> prp(n + 1, 0);
-  std::vector<int32_t> pci((size_t)H.nnz);
-  std::vector<double> pv((size_t)H.nnz);
+  HostBuf<int32_t> pci((size_t)H.nnz);
+  HostBuf<double> pv((size_t)H.nnz);
   int32_t w = 0;
   for (int64_t i = 0; i < n; ++i) {
     const int64_t o = dperm[i];
@@ -366,8 +383,8 @@ static am_status setup_impl(const am_csr* A, const int32_t* part, int32_t nparts
     }
   });
   d.ell_w = w;
-  std::vector<int32_t> ell_col((size_t)w * n);
-  std::vector<double> ell_val((size_t)w * n, 0.0);
+  HostBuf<int32_t> ell_col((size_t)w * n);
+  HostBuf<double> ell_val((size_t)w * n);
   parallel_for((n + 4095) / 4096, 1, [&](int64_t cb) {
     const int64_t hi = std::min<int64_t>(n, (cb + 1) * 4096);
     for (int64_t i = cb * 4096; i < hi; ++i)
@@ -378,6 +395,7 @@ static am_status setup_impl(const am_csr* A, const int32_t* part, int32_t nparts
           ell_val[(size_t)c * n + i] = pv[p];
         } else {
           ell_col[(size_t)c * n + i] = (int32_t)i;
+          ell_val[(size_t)c * n + i] = 0.0;
         }
       }
   });
@@ -405,51 +423,65 @@ static am_status setup_impl(const am_csr* A, const int32_t* part, int32_t nparts
   for (int32_t s2 = 0; s2 < st.m; ++s2)
     mbf_off[s2 + 1] = mbf_off[s2] + (st.isub_ptr[s2 + 1] - st.isub_ptr[s2]) *
                                         (st.sub_ptr[s2 + 1] - st.sub_ptr[s2]);
-  // boundary weights -B_s psi_n: entry k collects -2 a_e over the edges of E_n at k
+  // boundary weights -B_s psi_n: entry k collects -2 a_e over the edges of E_n
+  // at k.  The slot (n, side) lists the edges of E_n in order, sorted stably
+  // by local row and summed in that order; slots are independent, built in
+  // parallel and concatenated in slot order.
   std::vector<int32_t> e_kloc(d.NE), e_lloc(d.NE);
-  std::vector<std::vector<std::pair<int32_t, double>>> wts(npair);
-  for (int64_t nidx = 0; nidx < NL; ++nidx) {
+  parallel_for(NL, 64, [&](int64_t nidx) {
     const int32_t i = st.iface_ij[2 * nidx], j = st.iface_ij[2 * nidx + 1];
     for (int64_t e2 = st.iface_ptr[nidx]; e2 < st.iface_ptr[nidx + 1]; ++e2) {
-      const int32_t kl = dpos[st.edge_k[e2]] - (int32_t)st.sub_ptr[i];
-      const int32_t ll = dpos[st.edge_l[e2]] - (int32_t)st.sub_ptr[j];
-      e_kloc[e2] = kl;
-      e_lloc[e2] = ll;
-      wts[bidx[2 * nidx]].emplace_back(kl, -2.0 * st.edge_a[e2]);
-      wts[bidx[2 * nidx + 1]].emplace_back(ll, -2.0 * st.edge_a[e2]);
+      e_kloc[e2] = dpos[st.edge_k[e2]] - (int32_t)st.sub_ptr[i];
+      e_lloc[e2] = dpos[st.edge_l[e2]] - (int32_t)st.sub_ptr[j];
     }
+  });
+  std::vector<int64_t> pair_if(npair);
+  for (int64_t nidx = 0; nidx < NL; ++nidx) {
+    pair_if[bidx[2 * nidx]] = 2 * nidx;
+    pair_if[bidx[2 * nidx + 1]] = 2 * nidx + 1;
   }
-  std::vector<int64_t> bw_ptr(npair + 1, 0);
-  std::vector<int32_t> bw_row;
-  std::vector<double> bw_val;
-  for (int64_t pi = 0; pi < npair; ++pi) {
-    auto& v = wts[pi];
+  std::vector<std::vector<std::pair<int32_t, double>>> wts(npair);
+  parallel_for(npair, 16, [&](int64_t pi) {
+    const int64_t nidx = pair_if[pi] / 2;
+    const bool side1 = pair_if[pi] & 1;
+    std::vector<std::pair<int32_t, double>> v;
+    v.reserve((size_t)(st.iface_ptr[nidx + 1] - st.iface_ptr[nidx]));
+    for (int64_t e2 = st.iface_ptr[nidx]; e2 < st.iface_ptr[nidx + 1]; ++e2)
+      v.emplace_back(side1 ? e_lloc[e2] : e_kloc[e2], -2.0 * st.edge_a[e2]);
     std::stable_sort(v.begin(), v.end(),
                      [](const std::pair<int32_t, double>& a, const std::pair<int32_t, double>& b) {
                        return a.first < b.first;
                      });
+    auto& g = wts[pi];
     for (size_t t = 0; t < v.size(); ++t) {
       if (t > 0 && v[t].first == v[t - 1].first)
-        bw_val.back() += v[t].second;
-      else {
-        bw_row.push_back(v[t].first);
-        bw_val.push_back(v[t].second);
-      }
+        g.back().second += v[t].second;
+      else
+        g.push_back(v[t]);
     }
-    bw_ptr[pi + 1] = (int64_t)bw_row.size();
-    std::vector<std::pair<int32_t, double>>().swap(v);
-  }
+  });
+  std::vector<int64_t> bw_ptr(npair + 1, 0);
+  for (int64_t pi = 0; pi < npair; ++pi) bw_ptr[pi + 1] = bw_ptr[pi] + (int64_t)wts[pi].size();
+  std::vector<int32_t> bw_row((size_t)bw_ptr[npair]);
+  std::vector<double> bw_val((size_t)bw_ptr[npair]);
+  parallel_for(npair, 64, [&](int64_t pi) {
+    for (size_t t = 0; t < wts[pi].size(); ++t) {
+      bw_row[bw_ptr[pi] + t] = wts[pi][t].first;
+      bw_val[bw_ptr[pi] + t] = wts[pi][t].second;
+    }
+  });
+  std::vector<std::vector<std::pair<int32_t, double>>>().swap(wts);
 
   mark("host layout", nullptr);
 
   // ---- device upload ----
   std::vector<void*>& al = d.allocs;
   SCHK(upload(al, &d.dperm, dperm, sm));
-  SCHK(upload(al, &d.ell_col, ell_col, sm));
-  SCHK(upload(al, &d.ell_val, ell_val, sm));
+  SCHK(upload(al, &d.ell_col, ell_col.p.get(), ell_col.n, sm));
+  SCHK(upload(al, &d.ell_val, ell_val.p.get(), ell_val.n, sm));
   SCHK(upload(al, &d.prp, prp, sm));
-  SCHK(upload(al, &d.pci, pci, sm));
-  SCHK(upload(al, &d.pv, pv, sm));
+  SCHK(upload(al, &d.pci, pci.p.get(), pci.n, sm));
+  SCHK(upload(al, &d.pv, pv.p.get(), pv.n, sm));
   SCHK(upload(al, &d.sub_ptr, st.sub_ptr, sm));
   SCHK(upload(al, &d.wp, lp.wp, sm));
   SCHK(upload(al, &d.roff, lp.roff, sm));
@@ -472,8 +504,8 @@ static am_status setup_impl(const am_csr* A, const int32_t* part, int32_t nparts
   SCHK(upload(al, &d.e_lloc, e_lloc, sm));
   SCHK(upload(al, &d.e_a, st.edge_a, sm));
   SCHK(upload(al, &d.bdst, bdst, sm));
-  std::vector<double>().swap(ell_val);
-  std::vector<int32_t>().swap(ell_col);
+  ell_val.p.reset();
+  ell_col.p.reset();
   mark("uploads", sm);
 
   const size_t esz = d.prec == AM_FP64 ? 8 : (d.prec == AM_FP32 ? 4 : 2);

@@ -196,17 +196,49 @@ am_status build_structure(const HostCSR& A, const int32_t* part, int32_t nparts,
     std::vector<int64_t> fill(st.sub_ptr.begin(), st.sub_ptr.end() - 1);
     for (int64_t k = 0; k < n; ++k) st.perm[fill[part[k]]++] = (int32_t)k;
   }
-  // interface edges: stored a_kl != 0 with part[k] < part[l]
+  // interface edges: stored a_kl != 0 with part[k] < part[l], ordered by
+  // (part k, part l, k, l).  Counting sort by part k (rows in index order),
+  // then each part's edges sorted by (part l, k, l) on its own; the keys are
+  // unique, so the order is that of one sort over all edges.
   struct E { int32_t pk, pl, k, l; double a; };
-  std::vector<E> edges;
-  for (int64_t k = 0; k < n; ++k)
-    for (int64_t p = A.rp[k]; p < A.rp[k + 1]; ++p) {
-      int32_t l = A.ci[p];
-      double a = A.v[p];
-      if (a != 0.0 && part[k] < part[l]) edges.push_back({part[k], part[l], (int32_t)k, l, a});
+  auto is_edge = [&](int64_t k, int64_t p) {
+    return A.v[p] != 0.0 && part[k] < part[A.ci[p]];
+  };
+  constexpr int64_t kRows = 4096;
+  const int64_t nch = (n + kRows - 1) / kRows;
+  std::vector<int64_t> rcnt(n, 0);
+  parallel_for(nch, 1, [&](int64_t c) {
+    const int64_t hi = std::min(n, (c + 1) * kRows);
+    for (int64_t k = c * kRows; k < hi; ++k) {
+      int64_t e = 0;
+      for (int64_t p = A.rp[k]; p < A.rp[k + 1]; ++p) e += is_edge(k, p) ? 1 : 0;
+      rcnt[k] = e;
     }
-  std::sort(edges.begin(), edges.end(), [](const E& x, const E& y) {
-    return std::tie(x.pk, x.pl, x.k, x.l) < std::tie(y.pk, y.pl, y.k, y.l);
+  });
+  std::vector<int64_t> gptr(nparts + 1, 0);
+  for (int64_t k = 0; k < n; ++k) gptr[part[k] + 1] += rcnt[k];
+  for (int32_t i = 0; i < nparts; ++i) gptr[i + 1] += gptr[i];
+  std::vector<int64_t> rpos(n);
+  {
+    std::vector<int64_t> fill(gptr.begin(), gptr.end() - 1);
+    for (int64_t k = 0; k < n; ++k) {
+      rpos[k] = fill[part[k]];
+      fill[part[k]] += rcnt[k];
+    }
+  }
+  std::vector<E> edges((size_t)gptr[nparts]);
+  parallel_for(nch, 1, [&](int64_t c) {
+    const int64_t hi = std::min(n, (c + 1) * kRows);
+    for (int64_t k = c * kRows; k < hi; ++k) {
+      int64_t o = rpos[k];
+      for (int64_t p = A.rp[k]; p < A.rp[k + 1]; ++p)
+        if (is_edge(k, p)) edges[o++] = {part[k], part[A.ci[p]], (int32_t)k, A.ci[p], A.v[p]};
+    }
+  });
+  parallel_for(nparts, 1, [&](int64_t g) {
+    std::sort(edges.begin() + gptr[g], edges.begin() + gptr[g + 1], [](const E& x, const E& y) {
+      return std::tie(x.pl, x.k, x.l) < std::tie(y.pl, y.k, y.l);
+    });
   });
   const int64_t ne = (int64_t)edges.size();
   st.edge_k.resize(ne);
