@@ -100,6 +100,33 @@ def test_structure_bit_exact_random_mmatrix(seed):
     _check_structure(A, part, 6)
 
 
+def test_structure_independent_of_host_threads(monkeypatch):
+    """The host structure (validation, interface edges) runs on several host
+    threads; its output is the same for any thread count."""
+    A = _grid(48, 36, 12, distorted=True, seed=5)
+    part, m = partition_bisect(A.row_ptr, A.col, A.val, A.n, 200, 800, 3)
+    outs = []
+    for t in ("1", "8", "3"):
+        monkeypatch.setenv("ALGMORTAR_HOST_THREADS", t)
+        outs.append(am.structure(A, part, m))
+    for o in outs[1:]:
+        for k, v in outs[0].items():
+            assert np.array_equal(o[k], v), k
+    # the lowest failing row is named whatever the thread count
+    bad = CSR(n=A.n, row_ptr=A.row_ptr, col=A.col, val=A.val.copy())
+    rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+    offd = np.nonzero(A.col != rows)[0]
+    bad.val[offd[[2000, 9000]]] *= 2.0  # two asymmetric pairs
+    msgs = set()
+    for t in ("1", "8"):
+        monkeypatch.setenv("ALGMORTAR_HOST_THREADS", t)
+        with pytest.raises(AlgMortarError) as e:
+            am.structure(bad, part, m)
+        assert e.value.status_name == "AM_ERR_NOT_SYMMETRIC"
+        msgs.add(str(e.value))
+    assert len(msgs) == 1, msgs
+
+
 def _small():
     P = random_3d(4, 4, 2, 1.0, 0, block=(2, 2, 2))
     part, m = partition_blocks(P.dims, P.partition[1])

@@ -168,3 +168,28 @@ def test_more_rhs_than_the_handle_allows():
     ora = AlgMortarCPU(P.A, part)
     assert rel(cpu(h.apply(gpu(r))), ora.apply(r)) <= 1e-12
     h.close()
+
+
+def test_setup_independent_of_host_threads(monkeypatch):
+    """The host part of set-up (orderings, layout, boundary weights) runs on
+    several threads; handles set up with 1 and with 16 give the same S^-1 and
+    (with one pinned local-kernel layout) the same applies, bit for bit, on
+    a bisection partition with RCM local orderings."""
+    from oracle import partition_bisect
+    from workloads.grids import distorted_hex_faces
+    from workloads.tpfa import Faces, assemble
+    nx, ny, nz = 30, 24, 10
+    n = nx * ny * nz
+    f = Faces.from_dict(distorted_hex_faces(nx, ny, nz, 0.3, 4, [(0, 0, 0.0)]))
+    A, b = assemble(f, np.exp(np.random.default_rng(2).normal(size=n)), n)
+    part, m = partition_bisect(A.row_ptr, A.col, A.val, n, 200, 800, 4)
+    monkeypatch.setenv("ALGMORTAR_TILE", "0")
+    r = gpu(np.random.default_rng(3).standard_normal(n))
+    out = []
+    for t in ("1", "16"):
+        monkeypatch.setenv("ALGMORTAR_HOST_THREADS", t)
+        h = am.AlgMortar(A, part, m)
+        out.append((h.export_interface("Sinv"), cpu(h.apply(r))))
+        h.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
