@@ -172,7 +172,8 @@ am_status algmortar_setup(const am_csr* A, const int32_t* part, int32_t nparts,
  * device, the structure, partition, local orderings and layout are kept
  * (for a sequence of permeabilities on one grid, as in the differentiation
  * form).  A: row_ptr and col_idx (host) must equal the set-up's; val holds
- * the new values in the same order, host or device (values_on_device).  The
+ * the new values in the same order, on the host or (values_on_device) on the
+ * handle's device.  The
  * values must pass the set-up's checks (finite, positive diagonal, bitwise
  * symmetric, couplings not positive), and a coupling between two subdomains
  * must be nonzero exactly where it was at set-up (the interfaces are kept).
