@@ -370,6 +370,31 @@ def test_separate_interface_product_parity(name, max_nrhs):
     h.close()
 
 
+@pytest.mark.parametrize("name", ["layered", "bisect"])
+@pytest.mark.parametrize("separate", [False, True])
+def test_eight_column_path(name, separate):
+    """6 right-hand sides on a handle for 8 (the 8-column kernels: two column
+    groups in the SpMV, per-wave interface partials in the update, the
+    8-column local and interface kernels), fused and separate interface
+    solve: every column's apply to 1e-12 and three columns' PCG solutions
+    to 1e-8 with iterations within one of the oracle's."""
+    A, part, m, b, ora = setup_case(name)
+    h = am.AlgMortar(A, part, m, max_nrhs=8, separate_iface=separate)
+    rng = np.random.default_rng(12)
+    R = rng.standard_normal((6, A.n))
+    Z = cpu(h.apply(gpu(R)))
+    for k in range(6):
+        assert rel(Z[k], ora.apply(R[k])) <= 1e-12, k
+    X, info, _ = h.pcg(gpu(R), 1e-10)
+    X = cpu(X)
+    for k in (0, 3, 5):
+        res = pcg(lambda v: ora.As @ v, R[k], ora.apply, 1e-10)
+        assert info[k]["converged"] == 1
+        assert abs(info[k]["iterations"] - res.iterations) <= 1
+        assert rel(X[k], res.x) <= 1e-8, k
+    h.close()
+
+
 def test_time_kernel_rejects_separate_interface_on_fused_handle():
     """A handle whose interface solve runs inside the local kernel has no
     separate interface product: timing it is refused on the host (no launch)."""
