@@ -114,79 +114,140 @@ __global__ __launch_bounds__(256) void k_spmv_p(int64_t n, int w, const int32_t*
   double pq[KG];
 #pragma unroll
   for (int k = 0; k < KG; ++k) pq[k] = 0.0;
-  bool first = true;
   double beta[KG];
-  for (int64_t i0 = (int64_t)blk * blockDim.x; i0 < n; i0 += (int64_t)nblk * blockDim.x) {
-    const int64_t i = i0 + threadIdx.x;
-    const bool ok = i < n;
-    int64_t col[MAXW];
-    double v[MAXW];
-#pragma unroll
-    for (int c = 0; c < MAXW; ++c) {
-      col[c] = (ok && c < w) ? ec[(int64_t)c * n + i] : 0;
-      v[c] = (ok && c < w) ? ev[(int64_t)c * n + i] : 0.0;
-    }
-    double zc[MAXW][KG], pc[MAXW][KG], zi[KG], pi[KG];
+  // beta from the folded partials; the first workgroup of each group stores
+  // the scalars
+  auto set_beta = [&]() {
 #pragma unroll
     for (int k = 0; k < KG; ++k) {
-      zi[k] = ok ? z[vi(i, k)] : 0.0;
-      pi[k] = ok ? pold[vi(i, k)] : 0.0;
+      beta[k] = 0.0;
+      if (k0 + k >= nrhs || sdone[k]) continue;
+      const double rzn = rzq[k];
+      int done = 0;
+      if (!(rzn > 0.0)) {
+        done = 1;
+      } else if (sit[k] > 0) {
+        beta[k] = flexible ? -alph[k] * rzq[KG + k] / rzo[k] : rzn / rzo[k];
+      }
+      if (blk == 0 && threadIdx.x == 0) {
+        PcgScalars& S = sc[k0 + k];
+        S.rzv[parity] = rzn;
+        S.rz = rzn;
+        S.qz = rzq[KG + k];
+        S.beta = beta[k];
+        if (done) {
+          S.done = 1;
+          S.status = AM_ERR_BREAKDOWN;
+        }
+      }
     }
+  };
+  // p_new and q of row i from its ELL row (v), own values and gathers
+  auto finish_row = [&](int64_t i, const double (&v)[MAXW], const double (&zi)[KG],
+                        const double (&pi)[KG], const double (&zc)[MAXW][KG],
+                        const double (&pc)[MAXW][KG]) {
+    double acc[KG];
+#pragma unroll
+    for (int k = 0; k < KG; ++k) acc[k] = 0.0;
 #pragma unroll
     for (int c = 0; c < MAXW; ++c)
 #pragma unroll
-      for (int k = 0; k < KG; ++k) {
-        zc[c][k] = (c < w) ? z[vi(col[c], k)] : 0.0;
-        pc[c][k] = (c < w) ? pold[vi(col[c], k)] : 0.0;
-      }
-    if (first) {  // fold the (r, z), (q, z) partials while the gathers are in flight
-      first = false;
-      block_sum<2 * KG>(rzq, lds);
-      if (done_flag) return;  // uniform: every thread read the same flag
+      for (int k = 0; k < KG; ++k) acc[k] = fma(v[c], fma(beta[k], pc[c][k], zc[c][k]), acc[k]);
 #pragma unroll
-      for (int k = 0; k < KG; ++k) {
-        beta[k] = 0.0;
-        if (k0 + k >= nrhs || sdone[k]) continue;
-        const double rzn = rzq[k];
-        int done = 0;
-        if (!(rzn > 0.0)) {
-          done = 1;
-        } else if (sit[k] > 0) {
-          beta[k] = flexible ? -alph[k] * rzq[KG + k] / rzo[k] : rzn / rzo[k];
-        }
-        if (blk == 0 && threadIdx.x == 0) {
-          PcgScalars& S = sc[k0 + k];
-          S.rzv[parity] = rzn;
-          S.rz = rzn;
-          S.qz = rzq[KG + k];
-          S.beta = beta[k];
-          if (done) {
-            S.done = 1;
-            S.status = AM_ERR_BREAKDOWN;
-          }
-        }
-      }
+    for (int k = 0; k < KG; ++k) {
+      const double pn = fma(beta[k], pi[k], zi[k]);
+      pnew[vi(i, k)] = pn;
+      q[vi(i, k)] = acc[k];
+      pq[k] = fma(pn, acc[k], pq[k]);
     }
-    if (ok) {
-      double acc[KG];
+  };
+  const int64_t stride = (int64_t)nblk * blockDim.x;
+  if constexpr (KG <= 2 && MAXW <= 8) {
+    // Software pipeline over the rows of this thread: the ELL row and the
+    // own values of the next row are loaded while the gathers of the current
+    // row are in flight, so a row costs one memory round trip, not two.
+    // (With 4 columns per row the extra registers cost more than this saves.)
+    int32_t coln[MAXW];
+    double vn[MAXW], zin[KG], pin[KG];
+    auto load_row = [&](int64_t row) {
+      const bool okr = row < n;
 #pragma unroll
-      for (int k = 0; k < KG; ++k) acc[k] = 0.0;
+      for (int c = 0; c < MAXW; ++c) {
+        coln[c] = (okr && c < w) ? ec[(int64_t)c * n + row] : 0;
+        vn[c] = (okr && c < w) ? ev[(int64_t)c * n + row] : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < KG; ++k) {
+        zin[k] = okr ? z[vi(row, k)] : 0.0;
+        pin[k] = okr ? pold[vi(row, k)] : 0.0;
+      }
+    };
+    load_row((int64_t)blk * blockDim.x + threadIdx.x);
+    block_sum<2 * KG>(rzq, lds);  // with the first row in flight
+    if (done_flag) return;        // uniform: every thread read the same flag
+    set_beta();
+    for (int64_t i0 = (int64_t)blk * blockDim.x; i0 < n; i0 += stride) {
+      const int64_t i = i0 + threadIdx.x;
+      int32_t col[MAXW];
+      double v[MAXW], zi[KG], pi[KG];
+#pragma unroll
+      for (int c = 0; c < MAXW; ++c) {
+        col[c] = coln[c];
+        v[c] = vn[c];
+      }
+#pragma unroll
+      for (int k = 0; k < KG; ++k) {
+        zi[k] = zin[k];
+        pi[k] = pin[k];
+      }
+      double zc[MAXW][KG], pc[MAXW][KG];
 #pragma unroll
       for (int c = 0; c < MAXW; ++c)
 #pragma unroll
-        for (int k = 0; k < KG; ++k) acc[k] = fma(v[c], fma(beta[k], pc[c][k], zc[c][k]), acc[k]);
+        for (int k = 0; k < KG; ++k) {
+          zc[c][k] = (c < w) ? z[vi(col[c], k)] : 0.0;
+          pc[c][k] = (c < w) ? pold[vi(col[c], k)] : 0.0;
+        }
+      if (i0 + stride < n) load_row(i + stride);
+      if (i < n) finish_row(i, v, zi, pi, zc, pc);
+    }
+  } else {
+    bool first = true;
+    for (int64_t i0 = (int64_t)blk * blockDim.x; i0 < n; i0 += stride) {
+      const int64_t i = i0 + threadIdx.x;
+      const bool ok = i < n;
+      int64_t col[MAXW];
+      double v[MAXW];
+#pragma unroll
+      for (int c = 0; c < MAXW; ++c) {
+        col[c] = (ok && c < w) ? ec[(int64_t)c * n + i] : 0;
+        v[c] = (ok && c < w) ? ev[(int64_t)c * n + i] : 0.0;
+      }
+      double zc[MAXW][KG], pc[MAXW][KG], zi[KG], pi[KG];
 #pragma unroll
       for (int k = 0; k < KG; ++k) {
-        const double pn = fma(beta[k], pi[k], zi[k]);
-        pnew[vi(i, k)] = pn;
-        q[vi(i, k)] = acc[k];
-        pq[k] = fma(pn, acc[k], pq[k]);
+        zi[k] = ok ? z[vi(i, k)] : 0.0;
+        pi[k] = ok ? pold[vi(i, k)] : 0.0;
       }
+#pragma unroll
+      for (int c = 0; c < MAXW; ++c)
+#pragma unroll
+        for (int k = 0; k < KG; ++k) {
+          zc[c][k] = (c < w) ? z[vi(col[c], k)] : 0.0;
+          pc[c][k] = (c < w) ? pold[vi(col[c], k)] : 0.0;
+        }
+      if (first) {  // fold the (r, z), (q, z) partials while the gathers are in flight
+        first = false;
+        block_sum<2 * KG>(rzq, lds);
+        if (done_flag) return;  // uniform: every thread read the same flag
+        set_beta();
+      }
+      if (ok) finish_row(i, v, zi, pi, zc, pc);
     }
-  }
-  if (first) {  // a workgroup with no rows still folds (and may be the writer)
-    block_sum<2 * KG>(rzq, lds);
-    if (done_flag) return;
+    if (first) {  // a workgroup with no rows still folds (and may be the writer)
+      block_sum<2 * KG>(rzq, lds);
+      if (done_flag) return;
+    }
   }
   block_sum<KG>(pq, lds);
   if (threadIdx.x == 0)
