@@ -499,3 +499,24 @@ def test_two_columns_several_rows_per_thread():
     assert np.linalg.norm(X[0][idx] - ref) / np.linalg.norm(ref) <= 10 * max(gold["err_vs_tight"], 1e-9)
     tr = np.linalg.norm(P.b - P.A.to_scipy() @ X[0]) / np.linalg.norm(P.b)
     assert tr <= 2 * P.tol
+
+
+def test_pcg_ragged_rows_several_per_thread():
+    """One right-hand side on a 63 x 63 x 72 grid with 7 x 7 x 8 blocks
+    (285,768 rows: above 1024 x 256, so SpMV threads take two rows with the
+    second row's ELL entries loaded early, and not a multiple of 256, so the
+    last row block is partial), against the oracle's PCG."""
+    P = make_config("c4", nx=63, ny=63, nz=72, block=(7, 7, 8))
+    part, m = partition_blocks(P.dims, P.partition[1])
+    assert P.A.n > 1024 * 256 and P.A.n % 256 != 0
+    ora = AlgMortarCPU(P.A, part)
+    As = P.A.to_scipy()
+    ref = pcg(lambda v: As @ v, P.b, ora.apply, 1e-10)
+    h = am.AlgMortar(P.A, part, m)
+    x, info, _ = h.pcg(gpu(P.b), 1e-10)
+    x = cpu(x)
+    h.close()
+    assert info[0]["converged"] == 1
+    assert abs(info[0]["iterations"] - ref.iterations) <= 1
+    assert rel(x, ref.x) <= 1e-8
+    assert info[0]["true_rel_res"] <= 1e-9
