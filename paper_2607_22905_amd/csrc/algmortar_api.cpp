@@ -219,9 +219,12 @@ am_status algmortar_destroy(am_handle h) {
   for (void* p : h->sm_allocs) hipFree(p);
   if (h->bj) algmortar_destroy(h->bj);
   if (h->d.graph) hipGraphExecDestroy(h->d.graph);
+  for (hipGraphExec_t g : h->d.graph_short)
+    if (g) hipGraphExecDestroy(g);
   for (void* p : h->d.allocs) hipFree(p);
   for (void* p : h->vm.allocs) hipFree(p);
   if (h->d.h_flags) hipHostFree(h->d.h_flags);
+  if (h->d.h_sc) hipHostFree(h->d.h_sc);
   if (h->ev0) hipEventDestroy(h->ev0);
   if (h->ev1) hipEventDestroy(h->ev1);
   for (hipEvent_t e : h->evp)
@@ -557,6 +560,7 @@ static am_status setup_impl(const am_csr* A, const int32_t* part, int32_t nparts
   SCHK(hipMemsetAsync(d.red.counter, 0, 8 * sizeof(unsigned), sm));
   SCHK(hipMemsetAsync(d.shared, 0, sizeof(PcgShared), sm));
   SCHK(hipHostMalloc((void**)&d.h_flags, 4 * sizeof(int32_t), hipHostMallocDefault));
+  SCHK(hipHostMalloc((void**)&d.h_sc, 2 * kMaxNRHS * sizeof(PcgScalars), hipHostMallocDefault));
 
   mark("device allocations", sm);
 
@@ -1042,8 +1046,8 @@ am_status algmortar_local_solve(am_handle h, const double* r, double* pbar, void
 
 static constexpr int kChunk = 8;  // iterations per captured graph (even: p ping-pong)
 
-static hipError_t run_chunk(DeviceState& d, int nr, hipStream_t st) {
-  for (int it = 0; it < kChunk; ++it) {
+static hipError_t run_chunk(DeviceState& d, int nr, hipStream_t st, int len = kChunk) {
+  for (int it = 0; it < len; ++it) {
     hipError_t e = launch_pcg_iteration(d, nr, it & 1, st);
     if (e != hipSuccess) return e;
   }
@@ -1188,44 +1192,126 @@ static am_status pcg_impl(am_handle h, const double* b, double* x, int32_t nrhs,
   HCHK(launch_pcg_start(d, nr, st));
   const bool use_graph = !(h->opt.flags & AM_FLAG_NO_GRAPH) && !prof;
   if (use_graph && (d.graph == nullptr || d.graph_nrhs != nr)) {
-    if (d.graph) {
-      HCHK(hipGraphExecDestroy(d.graph));
-      d.graph = nullptr;
+    // chunks of 8 iterations, and of 2, 4 and 6 for the end of a solve
+    hipGraphExec_t* slots[4] = {&d.graph, &d.graph_short[0], &d.graph_short[1], &d.graph_short[2]};
+    const int lens[4] = {kChunk, 2, 4, 6};
+    for (int i = 0; i < 4; ++i) {
+      if (*slots[i]) {
+        HCHK(hipGraphExecDestroy(*slots[i]));
+        *slots[i] = nullptr;
+      }
     }
-    hipGraph_t g = nullptr;
-    HCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    hipError_t ce = run_chunk(d, nr, st);
-    hipError_t ee = hipStreamEndCapture(st, &g);
-    if (ce != hipSuccess) return fail(h, AM_ERR_HIP, std::string("capture: ") + hipGetErrorString(ce));
-    if (ee != hipSuccess) return fail(h, AM_ERR_HIP, std::string("end capture: ") + hipGetErrorString(ee));
-    hipError_t ie = hipGraphInstantiate(&d.graph, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
-    if (ie != hipSuccess) {
-      d.graph = nullptr;
-      return fail(h, AM_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(ie));
+    d.graph_nrhs = 0;
+    for (int i = 0; i < 4; ++i) {
+      hipGraph_t g = nullptr;
+      HCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      hipError_t ce = run_chunk(d, nr, st, lens[i]);
+      hipError_t ee = hipStreamEndCapture(st, &g);
+      if (ce != hipSuccess) return fail(h, AM_ERR_HIP, std::string("capture: ") + hipGetErrorString(ce));
+      if (ee != hipSuccess) return fail(h, AM_ERR_HIP, std::string("end capture: ") + hipGetErrorString(ee));
+      hipError_t ie = hipGraphInstantiate(slots[i], g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      if (ie != hipSuccess) {
+        *slots[i] = nullptr;
+        return fail(h, AM_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(ie));
+      }
     }
     d.graph_nrhs = nr;
   }
-  // Chunks of kChunk iterations; the stop flag of chunk c is copied to pinned
-  // memory behind it and read while chunk c+1 already runs (a chunk launched
-  // after convergence only runs early-exit launches).
-  const int max_chunks = maxit / kChunk + 2;
+  // Chunks of up to kChunk iterations (even lengths keep the p ping-pong
+  // aligned).  The scalars of chunk c are copied to pinned memory behind it
+  // and read while chunk c + 1 runs; a chunk launched after convergence runs
+  // only early-exit launches.  From the relative residuals seen at the ends
+  // of chunks the host predicts the iterations still needed (per column, at
+  // the rate of the last chunk, plus a margin of 2) and shortens the last
+  // chunks to that, or launches nothing until the running chunk is read when
+  // it is predicted to converge.  Only the number of early-exit launches
+  // depends on this, never the arithmetic of an iteration.
+  const int limit = (maxit / kChunk + 2) * kChunk;
   if (prof) {
     bool done = false;
-    for (int it = 0; it < max_chunks * kChunk && !done; ++it)
+    for (int it = 0; it < limit && !done; ++it)
       HCHK(profiled_iteration(h, nr, it & 1, *prof, done));
   }
-  for (int c = 0; c < max_chunks && !prof; ++c) {
-    if (use_graph)
-      HCHK(hipGraphLaunch(d.graph, st));
-    else
-      HCHK(run_chunk(d, nr, st));
-    HCHK(hipMemcpyAsync(d.h_flags + (c & 1), &d.shared->all_done, sizeof(int32_t),
-                        hipMemcpyDeviceToHost, st));
-    HCHK(hipEventRecord(h->evf[c & 1], st));
-    if (c > 0) {
-      HCHK(hipEventSynchronize(h->evf[(c - 1) & 1]));
-      if (d.h_flags[(c - 1) & 1]) break;
+  if (!prof) {
+    int prev_it[kMaxNRHS], last_it[kMaxNRHS];
+    double prev_r[kMaxNRHS], last_r[kMaxNRHS];
+    bool col_done[kMaxNRHS];
+    for (int k = 0; k < kMaxNRHS; ++k) {
+      prev_it[k] = last_it[k] = -1;
+      prev_r[k] = last_r[k] = 0.0;
+      col_done[k] = false;
+    }
+    int launched = 0, inflight = 0, c_launch = 0, c_read = 0;
+    bool done = false;
+    // reads the oldest chunk in flight: its stop state and residuals
+    auto read_oldest = [&]() -> hipError_t {
+      const int slot = c_read & 1;
+      hipError_t e = hipEventSynchronize(h->evf[slot]);
+      if (e != hipSuccess) return e;
+      ++c_read;
+      --inflight;
+      const PcgScalars* S = d.h_sc + (size_t)slot * kMaxNRHS;
+      bool all = true;
+      for (int k = 0; k < nrhs; ++k) {
+        col_done[k] = S[k].done != 0;
+        if (col_done[k]) continue;
+        all = false;
+        if (S[k].it != last_it[k]) {
+          prev_it[k] = last_it[k];
+          prev_r[k] = last_r[k];
+          last_it[k] = S[k].it;
+          last_r[k] = S[k].bb > 0.0 ? S[k].rr / S[k].bb : 0.0;
+        }
+      }
+      done = all;
+      return hipSuccess;
+    };
+    // iterations still needed beyond those launched; -1 when not predictable
+    auto remaining = [&]() -> int {
+      int need = -1;
+      for (int k = 0; k < nrhs; ++k) {
+        if (col_done[k]) continue;
+        if (last_it[k] < 0 || prev_it[k] < 0 || !(last_r[k] > 0.0) || !(prev_r[k] > last_r[k]))
+          return -1;  // a column with no usable history (or not reducing)
+        const double t2 = (double)tol * (double)tol;
+        double left = 0.0;
+        if (last_r[k] > t2) {
+          const double rate = std::log(last_r[k] / prev_r[k]) / (last_it[k] - prev_it[k]);
+          left = std::min(std::ceil(std::log(t2 / last_r[k]) / rate), 1e6);
+        }
+        need = std::max(need, last_it[k] + (int)left + 2 - launched);
+      }
+      return std::max(need, 0);
+    };
+    while (launched < limit) {
+      int len = kChunk;
+      const int rem = remaining();
+      if (rem >= 0 && rem < kChunk) len = (rem + 1) & ~1;  // even, at most kChunk
+      if (len == 0) {
+        if (inflight > 0) {  // predicted to converge in a chunk in flight: read it first
+          HCHK(read_oldest());
+          if (done) break;
+          continue;
+        }
+        len = 2;
+      }
+      len = std::min(len, limit - launched);
+      if (use_graph)
+        HCHK(hipGraphLaunch(len == kChunk ? d.graph : d.graph_short[len / 2 - 1], st));
+      else
+        HCHK(run_chunk(d, nr, st, len));
+      const int slot = c_launch & 1;
+      HCHK(hipMemcpyAsync(d.h_sc + (size_t)slot * kMaxNRHS, d.sc, sizeof(PcgScalars) * nr,
+                          hipMemcpyDeviceToHost, st));
+      HCHK(hipEventRecord(h->evf[slot], st));
+      ++c_launch;
+      ++inflight;
+      launched += len;
+      if (inflight == 2) {
+        HCHK(read_oldest());
+        if (done) break;
+      }
     }
   }
   }

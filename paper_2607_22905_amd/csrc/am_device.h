@@ -129,10 +129,12 @@ struct DeviceState {
   PcgScalars* sc = nullptr; // [kMaxNRHS]
   PcgShared* shared = nullptr;
   int32_t* h_flags = nullptr;  // pinned host mirror of shared
+  PcgScalars* h_sc = nullptr;  // pinned host copies of sc, two slots of kMaxNRHS
   Reduce red;
 
-  // captured PCG chunk
+  // captured PCG chunks of 8 iterations (graph) and of 2, 4, 6 (graph_short)
   hipGraphExec_t graph = nullptr;
+  hipGraphExec_t graph_short[3] = {nullptr, nullptr, nullptr};
   hipStream_t graph_stream = nullptr;
   int graph_nrhs = 0;
   const void* graph_key = nullptr;
