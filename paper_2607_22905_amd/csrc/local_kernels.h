@@ -493,7 +493,7 @@ __global__ __launch_bounds__(64 * G * W) void k_localt(
   __shared__ AT bvec[G][2][64 * NR];
   __shared__ int stop_s;
 
-  const int s = subs[blockIdx.x];
+  const int s = subs ? subs[blockIdx.x] : (int)blockIdx.x;  // null: the identity list
   const int64_t base = sub_ptr[s];
   const int N = (int)(sub_ptr[s + 1] - base);
   const int64_t ro = roff[s];
@@ -1351,9 +1351,12 @@ hipError_t localt_shape(DeviceState& d, const double* r, double* z, const double
   for (int bk = 0; bk < 2; ++bk) {
     const int nb = (int)d.bucket_sub[bk].size();
     if (!nb) continue;
+    // bucket 0 lists 0 .. m-1 in order when bucket 1 is empty: the kernel
+    // then takes its subdomain from blockIdx.x (one dependent load less)
+    const int32_t* subs_arg = (bk == 0 && d.bucket_sub[1].empty()) ? nullptr : d.d_bucket_sub[bk];
     auto go = [&](auto kern, int threads) {
       am_launch(d, bk == first_bk, bk == last_bk, kern, dim3(nb), dim3(threads), st,
-                d.d_bucket_sub[bk], d.sub_ptr, d.roff, d.fac_off, (const FT*)d.Lc,
+                subs_arg, d.sub_ptr, d.roff, d.fac_off, (const FT*)d.Lc,
                 (const IT*)d.invd, r, z, mode, d.isub_ptr, d.isub_list, d.mbf_off, d.mbf, eta,
                 d.q, d.red.pd, off, d.fuse_eta, d.Sinv, (int)d.NL, d.ldS, d.bpart, d.red.pb, d.m,
                 init, d.sc, d.shared, d.n);
