@@ -1,18 +1,24 @@
 """Benchmark: AlgMortar-PCG solves per second on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--config c2] [--prec fp64]
+    python bench.py [--steps K] [--warmup W] [--config c4] [--prec fp64]
 
-Workload (default): the 64^3 layered high-contrast TPFA system (contrast
-1e6), 512 subdomains of 8^3 cells, one right-hand side, PCG to relative
-residual 1e-8 with x0 = 0.  A step is one full PCG solve (every iteration:
-SpMV, dots, axpys and the AlgMortar apply -- local band sweeps, interface
-right-hand side, interface solve, reconstruction).  The set-up (partition,
-local factors, basis functions, interface matrix and its inverse) runs once
-before the timed region, as the factors are reused across solves; its time
-is reported as setup_ms.  Inputs are device resident when timing starts.
+Workload (default): the 128^3 TPFA system with K = exp(GRF, sigma 1, ell 8),
+4096 subdomains of 8^3 cells, one right-hand side, PCG to relative residual
+1e-8 with x0 = 0 (FP64 everywhere).  A step is one full PCG solve (every
+iteration: SpMV, dots, axpys and the AlgMortar apply -- local tile sweeps,
+interface right-hand side, interface solve, reconstruction).  The set-up
+(partition, local factors, basis functions, interface matrix and its
+inverse) runs once before the timed region, as the factors are reused
+across solves; its time is reported as setup_ms.  Inputs are device
+resident when timing starts.
+
+With FP64 local factors (the default) the same workload is also solved with
+FP32 and BF16 local factors (the precision form: interface solve, dots and
+residuals stay FP64), reported under "precision_forms" with their solve
+rates, iteration counts and speedups over FP64.
 
 Prints one JSON line with the metric, the roofline of the dominant kernel
-(the local band sweeps + reconstruction) and the CPU oracle baseline.
+(the local tile sweeps + reconstruction) and the CPU oracle baseline.
 """
 import argparse
 import hashlib
@@ -43,15 +49,19 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def traffic_record(prec, config):
+def traffic_record(prec, config, tile_choice):
     """HBM bytes per launch of the local kernel from committed rocprofv3
-    counter runs, valid only while the kernel source is unchanged."""
+    counter runs, valid only while the kernel source is unchanged and for the
+    wave layout the counters were taken with (the runs pin it with
+    ALGMORTAR_TILE; the record stores it as "tile_choice")."""
     path = os.path.join(ROOT, "profiles", f"k_local_{config}_{prec}_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     src = open(os.path.join(ROOT, "paper_2607_22905_amd", "csrc", "local_kernels.h"), "rb").read()
     if rec.get("local_kernels_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    if rec.get("tile_choice") != tile_choice:
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -104,34 +114,122 @@ def gradient_timing(P, part, m, steps):
     return out
 
 
-def cpu_baseline(P, part, iters, its_to_converge, smooth=None):
-    """The FP64 oracle on the host cores: set-up (untimed for the metric),
-    then a bounded sample of PCG iterations, extrapolated to a whole solve.
-    smooth: (blocks, steps) for the block-Jacobi-smoothed preconditioner."""
+# The oracle cannot finish the large workloads within the benchmark's time
+# limit (at 128^3: about two minutes of set-up and 4 s per PCG iteration on
+# eight cores), so it runs on a bounded sample: the same workload recipe at a
+# reduced grid (same field model, boundary conditions, sources and subdomain
+# shape), solved completely, and its time per PCG iteration is scaled to the
+# benchmarked grid by the ratio of cells.
+CPU_SAMPLE = {
+    "c4": dict(nx=64, ny=64, nz=64),
+    "c5": dict(nx=48, ny=48, nz=48),
+    "c3": dict(nx=64, ny=64, nz=32),
+}
+
+
+def _oracle_leg(S, part, threads, smooth):
+    """One timed oracle run (set-up, then PCG on the first right-hand side)
+    with the BLAS pool limited to `threads`."""
     import numpy as np
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle import AlgMortarCPU, pcg
     from oracle.smoothing import SmoothedAlgMortarCPU
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:
-        threads = os.cpu_count()
-    t0 = time.perf_counter()
-    pre = AlgMortarCPU(P.A, part)
+    with threadpool_limits(limits=threads):
+        blas = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        t0 = time.perf_counter()
+        pre = AlgMortarCPU(S.A, part)
+        if smooth is not None:
+            pre = SmoothedAlgMortarCPU(pre, smooth[0], smooth[1])
+        t_setup = time.perf_counter() - t0
+        As = S.A.to_scipy()
+        b0 = S.b if S.b.ndim == 1 else S.b[:, 0]
+        t0 = time.perf_counter()
+        res = pcg(lambda v: As @ v, b0, pre.apply, S.tol)
+        t_solve = time.perf_counter() - t0
+    return dict(threads=int(blas), setup_s=t_setup, solve_s=t_solve, iterations=res.iterations,
+                ms_per_iteration=t_solve / max(res.iterations, 1) * 1e3,
+                true_rel_res=res.true_rel_res)
+
+
+def cpu_baseline(config, P, its_to_converge, smooth=None, theta=None):
+    """The FP64 oracle on the host cores, in two legs (one thread, all
+    cores): set-up, a complete PCG solve and its iterations on the bounded
+    sample of CPU_SAMPLE (the workload itself where it is small), and the
+    solve rate scaled to the benchmarked workload (time per iteration times
+    the cell ratio, times the GPU's iteration count)."""
+    import numpy as np
+    from oracle import partition_blocks, partition_bisect
+    from workloads import make_config
+    kw = dict(CPU_SAMPLE.get(config, {}))
+    if theta is not None:
+        kw["theta"] = theta
+    if smooth is not None or not kw or config in ("c1",):
+        S, kw_used = P, {}
+    else:
+        S, kw_used = make_config(config, **kw), kw
+    if S.partition[0] == "blocks":
+        part, _ = partition_blocks(S.dims, S.partition[1])
+    else:
+        _, lo, hi, seed = S.partition
+        part, _ = partition_bisect(S.A.row_ptr, S.A.col, S.A.val, S.n, lo, hi, seed)
+    ncpu = os.cpu_count()
+    # the GPU box allots 16 host threads per GPU (OMP_NUM_THREADS)
+    allc = int(os.environ.get("OMP_NUM_THREADS", ncpu) or ncpu)
+    allc = max(1, min(allc, ncpu))
+    sm = None
     if smooth is not None:
-        pre = SmoothedAlgMortarCPU(pre, smooth[0], smooth[1])
-    t_setup = time.perf_counter() - t0
-    As = P.A.to_scipy()
-    t0 = time.perf_counter()
-    b0 = P.b if P.b.ndim == 1 else P.b[:, 0]  # the oracle solves one right-hand side at a time
-    res = pcg(lambda v: As @ v, b0, pre.apply, 1e-30, maxit=iters)
-    t_it = (time.perf_counter() - t0) / max(res.iterations, 1)
-    sps = 1.0 / (t_it * its_to_converge)
-    return dict(value=sps, unit="solves/s", cores=int(threads), kind="oracle",
-                sample=f"oracle set-up ({t_setup:.1f} s, not in the metric) then {res.iterations} "
-                       f"PCG iterations ({t_it * 1e3:.1f} ms each) extrapolated to "
-                       f"{its_to_converge} iterations per solve",
-                setup_s=t_setup)
+        sm = smooth
+    legs = [_oracle_leg(S, part, t, sm) for t in (1, allc)]
+    scale = P.n / S.n
+    for leg in legs:
+        leg["solves_per_s_scaled"] = 1.0 / (leg["ms_per_iteration"] * 1e-3 * scale * its_to_converge)
+    best = legs[-1]
+    sample = (f"the oracle on the {config} recipe at {S.dims[0]}x{S.dims[1]}x{S.dims[2]} "
+              f"({S.n} cells, 1/{scale:.0f} of the workload), set-up and one complete PCG "
+              f"solve ({best['iterations']} iterations) per leg; solves/s scaled by the cell "
+              f"ratio and the GPU's {its_to_converge} iterations"
+              if kw_used else
+              f"the oracle on the workload itself, set-up and one complete PCG solve per leg")
+    return dict(value=best["solves_per_s_scaled"], unit="solves/s", cores=best["threads"],
+                kind="oracle", sample=sample, os_cpu_count=ncpu, blas_threads_all_cores=best["threads"],
+                legs=legs)
+
+
+def precision_forms(P, part, m, b, x64, args, v64, its64):
+    """The precision form on the same workload: FP32 and BF16 local factors
+    (BF16: bf16 storage, fp32 arithmetic), FP64 interface solve, dots and
+    residuals; each timed like the FP64 run.  Reports solves/s, the speedup
+    over FP64, iterations (and their change) and the relative L2 distance of
+    the solution from the FP64 one (both at the workload's tolerance)."""
+    import numpy as np
+    import torch
+
+    import paper_2607_22905_amd as am
+    res = {}
+    nrhs = P.nrhs
+    for prec in ("fp32", "bf16"):
+        h = am.AlgMortar(P.A, part, m, prec=prec, graph=not args.no_graph, max_nrhs=nrhs)
+        x = torch.empty_like(b)
+        for _ in range(args.warmup):
+            h.pcg(b, P.tol, out=x)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, info, _ = h.pcg(b, P.tol, out=x)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        its = max(i["iterations"] for i in info)
+        v = args.steps * nrhs / el
+        err = float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))
+        res[prec] = {"value": v, "unit": "solves/s", "speedup_vs_fp64": v / v64,
+                     "ms_per_step": el / args.steps * 1e3, "iterations": its,
+                     "iteration_change_vs_fp64": its - its64,
+                     "true_rel_res": max(i["true_rel_res"] for i in info),
+                     "rel_l2_vs_fp64_solution": err,
+                     "local_tile_autotune": h.tile_choice(nrhs)[0]}
+        log(f"bench: {prec} local factors: {v:.1f} solves/s ({v / v64:.2f}x FP64), {its} iterations")
+        h.close()
+    return res
 
 
 def main():
@@ -139,10 +237,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="c2")
+    ap.add_argument("--config", default="c4")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=12)
+    ap.add_argument("--no-precision-forms", action="store_true",
+                    help="skip the FP32 / BF16 local-factor solves of the FP64 run")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--theta", type=float, default=None,
                     help="contrast sweep K -> K^theta (c2, c6)")
@@ -254,7 +353,8 @@ def main():
         + ", ".join(f"{k} {v['avg_launch_us']:.1f} us" for k, v in others.items())
         + f"); replayed alone: " + ", ".join(f"{k} {v * 1e3:.1f} us" for k, v in iso.items()))
     tile_choice, tile_us = h.tile_choice(nrhs)
-    traffic = traffic_record(args.prec, args.config) if smooth is None else None
+    traffic = traffic_record(args.prec, args.config, tile_choice) if smooth is None else None
+    x64 = x.clone()
     out = {
         "metric": "PCG solves/s to 1e-8 rel. residual; precond-apply HBM GB/s vs peak",
         "value": args.steps * nrhs / elapsed,
@@ -295,11 +395,13 @@ def main():
         "local_tile_autotune": {"choice": tile_choice, "candidate_us": tile_us},
     }
     h.close()
+    if args.prec == "fp64" and smooth is None and not args.no_precision_forms:
+        out["precision_forms"] = precision_forms(P, part, m, b, x64, args, out["value"], its)
     if args.grad > 0:
         out["gradient"] = gradient_timing(P, part, m, args.grad)
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(P, part, args.cpu_iters, its, smooth)
+        out["cpu_baseline"] = cpu_baseline(args.config, P, its, smooth, args.theta)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

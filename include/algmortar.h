@@ -25,7 +25,9 @@
  *    algmortar_apply is asynchronous on that stream (except its first call
  *    for a right-hand-side count, which runs the tile autotuner and
  *    synchronizes); algmortar_pcg and algmortar_adjoint_grad block until the
- *    solve ends (they report am_info).
+ *    solve ends (they report am_info).  Calls that work on the library's own
+ *    stream (set-up, update_values, pcg, adjoint_grad) first wait for the
+ *    work already queued on `stream`, the null stream included.
  *  - A handle is not thread-safe; distinct handles are independent.
  */
 #ifndef ALGMORTAR_H

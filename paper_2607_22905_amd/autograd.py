@@ -45,6 +45,11 @@ class DarcyModel:
         self.last_info = None
         self.reuse_handle = bool(reuse_handle)
         self._h = None
+        # which forward's values the shared handle holds: a forward stamps
+        # its solve with a new token; a backward whose token differs puts its
+        # own values back first (several forwards before one backward)
+        self._h_token = None
+        self._next_token = 0
 
     def assemble(self, logK):
         """(matrix view for AlgMortar, right-hand side f + q) on the device."""
@@ -65,9 +70,22 @@ class DarcyModel:
             h = AlgMortar(A, self.part, self.nparts, prec=self.prec)
             if self.reuse_handle:
                 self._h = h
+        if self.reuse_handle:
+            self._next_token += 1
+            self._h_token = self._next_token
         p, info, _ = h.pcg(f, self.tol, maxit=self.maxit)
         self.last_info = info[0]
         return p, h
+
+    def handle_for(self, logK, token):
+        """The handle holding the values of the forward stamped ``token``
+        (on a shared handle: put back with ``update_values`` if a later
+        forward replaced them)."""
+        if self.reuse_handle and self._h_token != token:
+            A, _ = self.assemble(logK)
+            self._h.update_values(A)
+            self._h_token = token
+        return self._h
 
     def close(self):
         if self._h is not None:
@@ -100,12 +118,16 @@ def _make_function():
             ctx.save_for_backward(logK, p)
             ctx.model = model
             ctx.handle = h
+            ctx.token = model._h_token
             return p
 
         @staticmethod
         def backward(ctx, grad_p):
             logK, p = ctx.saved_tensors
             model, h = ctx.model, ctx.handle
+            if model.reuse_handle:
+                # a later forward may have given the shared handle its values
+                h = model.handle_for(logK, ctx.token)
             try:
                 g, lam, info = adjoint_grad(h, model.tpfa, logK, p, grad_p.contiguous(),
                                             tol=model.adjoint_tol, maxit=model.maxit)

@@ -272,8 +272,11 @@ static am_status setup_impl(const am_csr* A, const int32_t* part, int32_t nparts
   HostCSR H;
   std::vector<double> vals;
   if (A && A->values_on_device) {
-    if (hipSetDevice(opt.device) != hipSuccess) {
-      fail(h, AM_ERR_HIP, "hipSetDevice failed");
+    // device values may still be written by work queued on the caller's
+    // stream (NULL: the null stream)
+    if (hipSetDevice(opt.device) != hipSuccess ||
+        hipStreamSynchronize((hipStream_t)stream) != hipSuccess) {
+      fail(h, AM_ERR_HIP, "hipSetDevice / caller stream synchronization failed");
       return bail(AM_ERR_HIP);
     }
   }
@@ -351,7 +354,9 @@ static am_status setup_impl(const am_csr* A, const int32_t* part, int32_t nparts
   SCHK(hipEventCreateWithFlags(&h->evf[0], hipEventDisableTiming));
   SCHK(hipEventCreateWithFlags(&h->evf[1], hipEventDisableTiming));
   hipStream_t sm = h->own;
-  if (stream) SCHK(hipStreamSynchronize((hipStream_t)stream));
+  // the caller's stream (NULL: the null stream) may still be writing A's
+  // values; the library's own stream does not wait for it by itself
+  SCHK(hipStreamSynchronize((hipStream_t)stream));
   mark("device context", nullptr);
 
   // ---- host-side layout ----
@@ -826,7 +831,10 @@ am_status algmortar_update_values(am_handle h, const am_csr* A, void* stream) {
     return fail(h, AM_ERR_ARG, "A's pattern differs from the one the handle was set up with");
   DeviceState& d = h->d;
   HCHK(hipSetDevice(d.device));
-  if (stream) HCHK(hipStreamSynchronize((hipStream_t)stream));
+  // work queued on the caller's stream (NULL: the null stream) may still be
+  // writing the new values; h->own is a non-blocking stream and does not
+  // wait for it by itself
+  HCHK(hipStreamSynchronize((hipStream_t)stream));
   hipStream_t st = h->own;
   HCHK(hipStreamSynchronize(st));
   if (!h->vm.built) {
@@ -1148,7 +1156,9 @@ static am_status pcg_impl(am_handle h, const double* b, double* x, int32_t nrhs,
   if (nrhs == 1) ld = h->d.n;
   DeviceState& d = h->d;
   HCHK(hipSetDevice(d.device));
-  if (stream) HCHK(hipStreamSynchronize((hipStream_t)stream));
+  // b is read on h->own, a non-blocking stream: wait for the caller's stream
+  // (NULL: the null stream, e.g. torch's default stream) to finish writing it
+  HCHK(hipStreamSynchronize((hipStream_t)stream));
   hipStream_t st = h->own;
   const int nr = pow2_at_least(nrhs);
   const int64_t nv = d.n * nr;

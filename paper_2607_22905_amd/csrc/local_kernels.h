@@ -541,7 +541,13 @@ __global__ __launch_bounds__(64 * G * W) void k_localt(
   };
 
   tile_load(0, 0);
-  if (mode == 2 && all_done(sh)) return;  // (after the first tile is in flight)
+  // Early exit of a solve that has stopped.  With the interface solve fused
+  // in, workgroup 0 of this very launch may write all_done while the other
+  // workgroups read it, so a per-wave read could split a workgroup; there the
+  // decision comes from the stop test below, which every wave evaluates on
+  // the same partials, and is shared through stop_s after the barrier.
+  // Without it, all_done was written by an earlier launch and is uniform.
+  if (mode == 2 && !fuse_eta && all_done(sh)) return;  // (after the first tile is in flight)
   // ---- stop test and eta (every wave takes part) ----
   // Fused interface solve: wave v forms, for every row q of this subdomain,
   // the partial dot of S^{-1}[I_s[q], m] with b_m over its share of the

@@ -204,3 +204,30 @@ def test_darcy_model_reusing_its_handle():
         assert np.array_equal(grads[0], grads[1])
     for model in models:
         model.close()
+
+
+def test_darcy_model_two_forwards_then_backward():
+    """Two forward solves on a model that reuses its handle, then the first
+    forward's backward: the handle holds the second permeability by then, so
+    the backward must put the first one's values back.  The gradients equal
+    those of a model with a handle per solve."""
+    nx, ny, nz = 16, 16, 12
+    faces = Faces.from_dict(cartesian_faces(nx, ny, nz, [(0, 0, 1.0), (0, 1, 0.0)]))
+    n = nx * ny * nz
+    part, m = partition_blocks((nx, ny, nz), (8, 8, 6))
+    obs = torch.as_tensor(np.random.default_rng(4).choice(n, 200, replace=False), device=DEV)
+    lks = [gpu(grf((nz, ny, nx), 3.0, 1.0, seed).ravel()) for seed in (21, 22)]
+    grads = {}
+    for reuse in (False, True):
+        model = am.DarcyModel(faces, n, part, m, reuse_handle=reuse)
+        xs = [lk.clone().requires_grad_(True) for lk in lks]
+        ps = [am.AlgMortarSolve.apply(x, model) for x in xs]  # both forwards first
+        (ps[0][obs] ** 2).sum().backward()                      # then the first backward
+        (ps[1][obs] ** 2).sum().backward()
+        grads[reuse] = [cpu(x.grad) for x in xs]
+        model.close()
+    for k in range(2):
+        assert np.array_equal(grads[False][k], grads[True][k])
+    # and the two permeabilities give different gradients (the test would not
+    # see a handle that kept the wrong values otherwise)
+    assert not np.allclose(grads[True][0], grads[True][1])
