@@ -21,7 +21,15 @@ the shared input generators).
   finite-difference cells (drawn among cells with |g| >= 1e-3 max|g|), and
   the gradient's norm and maximum.  All oracle solves at tol 1e-12.
 
-    python tests/golden/make_golden.py [structure|c2|c5|c4]
+* ``full_c2.npz``, ``full_c4.npz``, ``full_c3.npz``: the three large
+  workloads at full size, at 4096 seeded cells (sample seed 17) with the
+  full vectors' L2 norms and maximum magnitudes.  Applies of the workload's
+  right-hand side(s) and seeded N(0,1) vectors; PCG solutions at tol 1e-10
+  with their iteration counts; for the 64^3 layered workload (contrast 1e6)
+  also a reference solve at tol 1e-13.  The 16-RHS irregular workload keeps
+  columns 0, 5 and 15 (its oracle solves one column at a time).
+
+    python tests/golden/make_golden.py [structure|c2|c5|c4|full_c2|full_c4|full_c3]
 """
 import hashlib
 import json
@@ -149,8 +157,69 @@ def c4_record():
     print("c4", res.iterations, tight.iterations, rec["err_vs_tight"])
 
 
+FULL_SAMPLE_SEED = 17
+FULL_SAMPLE = 4096
+FULL_APPLY_SEEDS = (101, 102, 103)
+FULL_C3_COLUMNS = (0, 5, 15)
+
+
+def full_record(name):
+    """Oracle applies and tol-1e-10 PCG solutions of a large workload at full
+    size, sampled at FULL_SAMPLE seeded cells (see the module docstring)."""
+    import time
+    P = make_config(name)
+    if P.partition[0] == "blocks":
+        part, _ = partition_blocks(P.dims, P.partition[1])
+    else:
+        _, lo, hi, seed = P.partition
+        part, _ = partition_bisect(P.A.row_ptr, P.A.col, P.A.val, P.n, lo, hi, seed)
+    t0 = time.time()
+    pre = AlgMortarCPU(P.A, part)
+    print(name, "oracle set-up", round(time.time() - t0), "s", flush=True)
+    As = P.A.to_scipy()
+    idx = np.sort(np.random.default_rng(FULL_SAMPLE_SEED).choice(P.n, size=FULL_SAMPLE, replace=False))
+    cols = FULL_C3_COLUMNS if P.b.ndim == 2 else (None,)
+    rhs = [P.b if c is None else P.b[:, c] for c in cols]
+    vecs, labels = list(rhs), [f"b{'' if c is None else c}" for c in cols]
+    for sd in (FULL_APPLY_SEEDS if P.b.ndim == 1 else FULL_APPLY_SEEDS[:1]):
+        vecs.append(np.random.default_rng(sd).standard_normal(P.n))
+        labels.append(f"normal{sd}")
+    out = dict(sample_idx=idx.astype(np.int64), apply_labels=np.array(labels),
+               rhs_columns=np.array([-1 if c is None else c for c in cols], dtype=np.int64))
+    za = []
+    for v in vecs:
+        z = pre.apply(v)
+        za.append((z[idx], np.linalg.norm(z), np.abs(z).max()))
+    out["apply_sample"] = np.array([a[0] for a in za])
+    out["apply_norm"] = np.array([a[1] for a in za])
+    out["apply_maxabs"] = np.array([a[2] for a in za])
+    print(name, "applies done", flush=True)
+    xs, its, nrm, mx, trr = [], [], [], [], []
+    for b in rhs:
+        t0 = time.time()
+        res = pcg(lambda v: As @ v, b, pre.apply, 1e-10)
+        print(name, "pcg 1e-10", res.iterations, res.true_rel_res, round(time.time() - t0), "s", flush=True)
+        xs.append(res.x[idx])
+        its.append(res.iterations)
+        nrm.append(np.linalg.norm(res.x))
+        mx.append(np.abs(res.x).max())
+        trr.append(res.true_rel_res)
+    out.update(x_sample=np.array(xs), iterations=np.array(its, dtype=np.int64),
+               x_norm=np.array(nrm), x_maxabs=np.array(mx), true_rel_res=np.array(trr),
+               tol=np.float64(1e-10))
+    if name == "c2":
+        ref = pcg(lambda v: As @ v, rhs[0], pre.apply, 1e-13)
+        print(name, "pcg 1e-13", ref.iterations, ref.true_rel_res, flush=True)
+        out.update(ref_x_sample=ref.x[idx][None, :], ref_iterations=np.array([ref.iterations]),
+                   ref_x_norm=np.array([np.linalg.norm(ref.x)]), ref_tol=np.float64(1e-13))
+    np.savez(os.path.join(HERE, f"full_{name}.npz"), **out)
+
+
 if __name__ == "__main__":
     which = sys.argv[1:] or ["structure", "c2", "c5", "c4"]
+    for name in ("c2", "c4", "c3"):
+        if f"full_{name}" in which:
+            full_record(name)
     if "structure" in which:
         main()
     if "c2" in which:
