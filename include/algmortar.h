@@ -219,6 +219,26 @@ am_status algmortar_set_smoother(am_handle h, const int32_t* blocks, int32_t nbl
 am_status algmortar_apply(am_handle h, const double* r, double* z, int32_t nrhs, int64_t ld,
                           void* stream);
 
+/* Allocation-free variant of algmortar_apply, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments and result as
+ * algmortar_apply (the same kernels: bitwise the same z), but its work
+ * buffers -- the permuted r and z, the interface slots, eta and the row-part
+ * sums of the interface product -- live in a static device array of
+ * 48 MiB (6,291,456 doubles) per GPU instead of the handle's memory, and the
+ * call allocates nothing.  The array is shared by every handle and every call
+ * on one GPU and keeps the last call's contents: calls that overlap on one
+ * GPU (other streams, other threads) race and must be ordered by the caller.
+ * Needs 2 n nr + 2 NL nr + ldS nr (+ P ldS nr with a separate interface
+ * product) doubles, nr = nrhs rounded up to a power of two; AM_ERR_ARG when
+ * that exceeds the array.  AM_ERR_UNSUPPORTED while a smoother is set.  Its
+ * first call for a right-hand-side count on a handle whose local-kernel
+ * layout is not yet chosen runs the autotuner and synchronizes (call
+ * algmortar_tile_choice first to keep it asynchronous).  Asynchronous on
+ * stream. */
+am_status algmortar_apply_static(am_handle h, const double* r, double* z, int32_t nrhs, int64_t ld,
+                                 void* stream);
+
 /* The local particular solutions only: pbar_i = A_i^{-1} r_i on every
  * subdomain (eq. def-pbar-local).  r, pbar: device, original ordering,
  * single column.  Asynchronous. */

@@ -55,6 +55,7 @@ _SIGS = {
     "am_structure": [POINTER(AmCsr), c_void_p, c_int32, c_int32] + [c_void_p] * 6,
     "algmortar_setup": [POINTER(AmCsr), c_void_p, c_int32, POINTER(AmOptions), c_void_p, POINTER(c_void_p)],
     "algmortar_apply": [c_void_p, c_void_p, c_void_p, c_int32, c_int64, c_void_p],
+    "algmortar_apply_static": [c_void_p, c_void_p, c_void_p, c_int32, c_int64, c_void_p],
     "algmortar_local_solve": [c_void_p, c_void_p, c_void_p, c_void_p],
     "algmortar_set_smoother": [c_void_p, c_void_p, c_int32, c_int32, c_void_p],
     "algmortar_update_values": [c_void_p, POINTER(AmCsr), c_void_p],

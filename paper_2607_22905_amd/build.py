@@ -30,6 +30,7 @@ SOURCES = [
     "kernels_pcg.hip",
     "kernels_smooth.hip",
     "kernels_tpfa.hip",
+    "static_scratch.hip",
 ]
 
 ARCH = os.environ.get("ALGMORTAR_ARCH", "gfx950")

@@ -348,6 +348,10 @@ static am_status setup_impl(const am_csr* A, const int32_t* part, int32_t nparts
   } while (0)
 
   SCHK(hipSetDevice(d.device));
+  // the device's address of the static scratch of algmortar_apply_static
+  // (looked up once per device; a failure is reported by that entry point,
+  // which looks it up again, and does not affect the rest of the library)
+  (void)static_scratch_init(d.device);
   SCHK(hipStreamCreateWithFlags(&h->own, hipStreamNonBlocking));
   SCHK(hipEventCreate(&h->ev0));
   SCHK(hipEventCreate(&h->ev1));
@@ -1036,6 +1040,91 @@ am_status algmortar_apply(am_handle h, const double* r, double* z, int32_t nrhs,
     }
     HCHK(launch_local_sweep(d, d.r, d.z, d.eta, nr, 1, st));
   }
+  HCHK(launch_permute_out(d.dperm, d.n, d.z, z, ld, nrhs, st));
+  return AM_OK;
+}
+
+// Scratch layout of algmortar_apply_static inside the static array: the
+// permuted input and output (n x nr each), the interface slots (2 NL x nr),
+// eta (ldS x nr) and, when the interface solve is its own launches, the
+// row-part sums (op_parts x ldS x nr); each piece starts on a 256-byte
+// boundary.  Returns the doubles needed.
+static int64_t static_layout(const DeviceState& d, int nr, double* base, double** r, double** z,
+                             double** bpart, double** eta, double** ypart) {
+  int64_t off = 0;
+  auto take = [&](int64_t count, double** out) {
+    if (out) *out = base ? base + off : nullptr;
+    off += (count + 31) / 32 * 32;
+  };
+  take(d.n * nr, r);
+  take(d.n * nr, z);
+  if (d.NL > 0) {
+    take(2 * d.NL * nr, bpart);
+    take((int64_t)d.ldS * nr, eta);
+    if (!d.fuse_eta) take((int64_t)d.op_parts * d.ldS * nr, ypart);
+  }
+  return off;
+}
+
+am_status algmortar_apply_static(am_handle h, const double* r, double* z, int32_t nrhs, int64_t ld,
+                                 void* stream) {
+  am_status s = check_vec_args(h, r, z, nrhs, ld);
+  if (s != AM_OK) return s;
+  if (nrhs == 1) ld = h->d.n;
+  if (h->sm.steps > 0)
+    return fail(h, AM_ERR_UNSUPPORTED, "algmortar_apply_static does not cover block-Jacobi smoothing");
+  DeviceState& d = h->d;
+  const int nr = pow2_at_least(nrhs);
+  const int64_t need = static_layout(d, nr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+  if (need > kStaticScratchDoubles)
+    return fail(h, AM_ERR_ARG,
+                "algmortar_apply_static needs " + std::to_string(need * 8) +
+                    " bytes of scratch for this handle and nrhs; its static scratch holds " +
+                    std::to_string(kStaticScratchDoubles * 8) + " bytes");
+  HCHK(hipSetDevice(d.device));
+  double* base = static_scratch_ptr(d.device);
+  if (!base) {  // first use on this device: the set-up's look-up did not succeed
+    HCHK(static_scratch_init(d.device));
+    base = static_scratch_ptr(d.device);
+    if (!base) return fail(h, AM_ERR_HIP, "no address for the static scratch on this device");
+  }
+  hipStream_t st = (hipStream_t)stream;
+  if (d.tile_cand[tile_slot(nr)] < 0) {
+    HCHK(hipStreamSynchronize(st));
+    am_status ts = autotune_tiles(h, nr);
+    if (ts != AM_OK) return ts;
+  }
+  double *sr, *sz, *sb = nullptr, *se = nullptr, *sy = nullptr;
+  static_layout(d, nr, base, &sr, &sz, &sb, &se, &sy);
+  // the launchers read the work buffers from the handle's state: point them
+  // at the static scratch for this call and put the handle's own back after
+  struct Swap {
+    DeviceState& d;
+    double *r, *z, *bpart, *eta, *ypart;
+    ~Swap() {
+      d.r = r;
+      d.z = z;
+      d.bpart = bpart;
+      d.eta = eta;
+      d.ypart = ypart;
+    }
+  } keep{d, d.r, d.z, d.bpart, d.eta, d.ypart};
+  d.r = sr;
+  d.z = sz;
+  if (d.NL > 0) {
+    d.bpart = sb;
+    d.eta = se;
+    if (!d.fuse_eta) d.ypart = sy;
+  }
+  // columns nrhs .. nr-1 of the padded block: zeros (the array keeps the last
+  // call's contents)
+  if (nrhs < nr) HCHK(launch_fill(d.r, d.n * nr, 0.0, st));
+  HCHK(launch_permute_in(d.dperm, d.n, r, ld, d.r, nrhs, st));
+  if (d.NL > 0) {
+    HCHK(launch_bpart(d, d.r, nr, st));
+    if (!d.fuse_eta) HCHK(launch_iface_gemv(d, nr, 0, 0, st));
+  }
+  HCHK(launch_local_sweep(d, d.r, d.z, d.eta, nr, 1, st));
   HCHK(launch_permute_out(d.dperm, d.n, d.z, z, ld, nrhs, st));
   return AM_OK;
 }

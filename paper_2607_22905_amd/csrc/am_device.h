@@ -15,6 +15,8 @@ namespace am {
 constexpr int kMaxNRHS = 16;
 constexpr int kMaxWp = 128;   // widest band window the LDS factor kernel holds
 constexpr int kTile = 64;     // dense interface-matrix tile
+// size of the static scratch of algmortar_apply_static (48 MiB of doubles)
+constexpr int64_t kStaticScratchDoubles = (int64_t)48 * 1024 * 1024 / 8;
 
 // PCG scalars of one right-hand side, device resident.
 struct PcgScalars {
@@ -140,6 +142,13 @@ struct DeviceState {
   const void* graph_key = nullptr;
   std::vector<void*> allocs;
 };
+
+// ---- static scratch (static_scratch.hip) ----
+// address of the device's copy of the static scratch array, looked up once
+// per device with `device` current (hipGetSymbolAddress)
+hipError_t static_scratch_init(int device);
+// that address, or null before static_scratch_init succeeded on `device`
+double* static_scratch_ptr(int device);
 
 // ---- launchers (kernels_local.hip) ----
 hipError_t launch_band_factor(DeviceState& d, hipStream_t s);

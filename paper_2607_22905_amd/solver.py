@@ -171,6 +171,16 @@ class AlgMortar:
                                      self.n, _stream(stream)), self._h)
         return z
 
+    def apply_static(self, r, out=None, stream=None):
+        """The allocation-free form of ``apply``: the same result, with the
+        library's work buffers in its static device scratch."""
+        import torch
+        k = _vec(r, self.n)
+        z = torch.empty_like(r) if out is None else out
+        check(load().algmortar_apply_static(self._h, c_void_p(r.data_ptr()), c_void_p(z.data_ptr()),
+                                            k, self.n, _stream(stream)), self._h)
+        return z
+
     def local_solve(self, r, stream=None):
         import torch
         _vec(r, self.n)
