@@ -92,6 +92,12 @@ typedef struct {
 /* apply eta = S^{-1} b as its own launches (row-part products, then their sum)
  * even where S^{-1} is small enough to be applied inside the local kernel */
 #define AM_FLAG_SEPARATE_IFACE 2u
+/* where eta = S^{-1} b is its own launches: multiply by the dense explicit
+ * S^{-1} instead of the nested-dissection block elimination (the default:
+ * explicit inverses of the uncoupled diagonal blocks of S in a nested-
+ * dissection order of the interfaces and of the Schur complement on the
+ * separators above them; Sec. 4, Corollary cor-schur-eta) */
+#define AM_FLAG_DENSE_IFACE 4u
 
 typedef struct {
   int32_t iterations;  /* PCG iterations (matrix products) performed */
@@ -151,6 +157,19 @@ am_status am_structure_sizes(const am_csr* A, const int32_t* part, int32_t npart
 am_status am_structure(const am_csr* A, const int32_t* part, int32_t nparts, int32_t mortar,
                        int32_t* perm, int64_t* sub_ptr, int64_t* iface_ptr, int32_t* iface_ij,
                        int32_t* edge_k, int32_t* edge_l);
+
+/* The nested-dissection order of the interface system that the interface
+ * solve uses when it runs as its own launches (host only; Sec. 4: S is
+ * coupled exactly where two basis functions share a subdomain, so cutting
+ * the subdomain graph splits the basis functions into two uncoupled sets and
+ * a separator).  order[NL] (host, out): ND position -> basis function, the
+ * rows of the nblk mutually uncoupled diagonal blocks first, then the ntop
+ * separator rows above them; blk_off (host, out, NL + 1 entries): the
+ * blocks' first positions and the end of the last block.  max_nrhs as at
+ * set-up (it bounds the block size).  AM_ERR_UNSUPPORTED when no dissection
+ * depth fits the kernels (the set-up then uses the dense explicit S^{-1}). */
+am_status am_interface_nd(const am_csr* A, const int32_t* part, int32_t nparts, int32_t max_nrhs,
+                          int32_t* order, int64_t* blk_off, int32_t* nblk, int64_t* ntop);
 
 /* ---- device entry points ---- */
 
@@ -229,9 +248,10 @@ am_status algmortar_apply(am_handle h, const double* r, double* z, int32_t nrhs,
  * call allocates nothing.  The array is shared by every handle and every call
  * on one GPU and keeps the last call's contents: calls that overlap on one
  * GPU (other streams, other threads) race and must be ordered by the caller.
- * Needs 2 n nr + 2 NL nr + ldS nr (+ P ldS nr with a separate interface
- * product) doubles, nr = nrhs rounded up to a power of two; AM_ERR_ARG when
- * that exceeds the array.  AM_ERR_UNSUPPORTED while a smoother is set.  Its
+ * Needs 2 n nr + 2 NL nr + ldS nr doubles (plus, where the interface solve
+ * is its own launches, its part sums and, in the dissection form, the block
+ * and separator vectors), nr = nrhs rounded up to a power of two; AM_ERR_ARG
+ * when that exceeds the array.  AM_ERR_UNSUPPORTED while a smoother is set.  Its
  * first call for a right-hand-side count on a handle whose local-kernel
  * layout is not yet chosen runs the autotuner and synchronizes (call
  * algmortar_tile_choice first to keep it asynchronous).  Asynchronous on

@@ -16,6 +16,7 @@ PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 MORTAR = {"interface": 0, "edge": 1}
 AM_FLAG_NO_GRAPH = 1
 AM_FLAG_SEPARATE_IFACE = 2
+AM_FLAG_DENSE_IFACE = 4
 
 
 class AmCsr(ctypes.Structure):
@@ -53,6 +54,8 @@ _SIGS = {
     "am_partition_bisect": [POINTER(AmCsr), c_int32, c_int32, c_uint64, c_void_p, POINTER(c_int32)],
     "am_structure_sizes": [POINTER(AmCsr), c_void_p, c_int32, c_int32, POINTER(c_int64), POINTER(c_int64)],
     "am_structure": [POINTER(AmCsr), c_void_p, c_int32, c_int32] + [c_void_p] * 6,
+    "am_interface_nd": [POINTER(AmCsr), c_void_p, c_int32, c_int32, c_void_p, c_void_p,
+                        POINTER(c_int32), POINTER(c_int64)],
     "algmortar_setup": [POINTER(AmCsr), c_void_p, c_int32, POINTER(AmOptions), c_void_p, POINTER(c_void_p)],
     "algmortar_apply": [c_void_p, c_void_p, c_void_p, c_int32, c_int64, c_void_p],
     "algmortar_apply_static": [c_void_p, c_void_p, c_void_p, c_int32, c_int64, c_void_p],

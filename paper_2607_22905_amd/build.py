@@ -20,6 +20,7 @@ LIB = os.environ.get("ALGMORTAR_LIB", os.path.join(HERE, "libalgmortar.so"))
 
 SOURCES = [
     "host_structure.cpp",
+    "iface_nd.cpp",
     "algmortar_api.cpp",
     "kernels_local.hip",
     "kernels_values.hip",
@@ -27,6 +28,7 @@ SOURCES = [
     "kernels_local_f32.hip",
     "kernels_local_bf16.hip",
     "kernels_iface.hip",
+    "kernels_nd.hip",
     "kernels_pcg.hip",
     "kernels_smooth.hip",
     "kernels_tpfa.hip",

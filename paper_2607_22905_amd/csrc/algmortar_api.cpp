@@ -207,6 +207,24 @@ am_status am_structure(const am_csr* A, const int32_t* part, int32_t nparts, int
   return AM_OK;
 }
 
+am_status am_interface_nd(const am_csr* A, const int32_t* part, int32_t nparts, int32_t max_nrhs,
+                          int32_t* order, int64_t* blk_off, int32_t* nblk, int64_t* ntop) {
+  if (!order || !blk_off || !nblk || !ntop || max_nrhs < 1 || max_nrhs > kMaxNRHS)
+    return fail(nullptr, AM_ERR_ARG, "bad argument");
+  Structure st;
+  am_status s = host_structure(A, part, nparts, AM_MORTAR_PER_INTERFACE, st);
+  if (s != AM_OK) return s;
+  IfaceND nd;
+  std::string e;
+  s = build_iface_nd(st, nd_max_rows(pow2_at_least(max_nrhs)), 1.15, nd, e);
+  if (s != AM_OK) return fail(nullptr, s, e);
+  std::copy(nd.order.begin(), nd.order.end(), order);
+  std::copy(nd.blk_off.begin(), nd.blk_off.end(), blk_off);
+  *nblk = nd.nblk;
+  *ntop = nd.ntop;
+  return AM_OK;
+}
+
 // ---------------------------------------------------------------------------
 am_status algmortar_destroy(am_handle h) {
   if (!h) return AM_OK;
@@ -234,6 +252,128 @@ am_status algmortar_destroy(am_handle h) {
   if (h->own) hipStreamDestroy(h->own);
   delete h;
   return AM_OK;
+}
+
+// Device arrays of the nested-dissection interface solve from its host
+// layout (structure only; nd_numeric fills the values).
+static hipError_t nd_upload(DeviceState& d, const IfaceND& ndh, hipStream_t sm) {
+  NdDevice& nd = d.nd;
+  std::vector<void*>& al = d.allocs;
+  const int64_t NL = d.NL;
+  nd.nblk = ndh.nblk;
+  nd.nrows = ndh.nrows;
+  nd.R = (int32_t)ndh.ntop;
+  nd.ldC = (int32_t)((ndh.ntop + 63) / 64 * 64);
+  nd.ldp = (int32_t)ndh.ld;
+  nd.h_blk_off = ndh.blk_off;
+  nd.h_pad_off = ndh.pad_off;
+  // padded position -> basis function
+  nd.h_src.assign((size_t)nd.ldp, -1);
+  for (int b = 0; b < nd.nblk; ++b)
+    for (int64_t r = ndh.blk_off[b]; r < ndh.blk_off[b + 1]; ++r)
+      nd.h_src[ndh.pad_off[b] + (r - ndh.blk_off[b])] = ndh.order[r];
+  for (int64_t t = 0; t < ndh.ntop; ++t) nd.h_src[ndh.pad_off[nd.nblk] + t] = ndh.order[nd.nrows + t];
+  std::vector<int64_t> inv_off(nd.nblk + 1, 0);
+  std::vector<int32_t> wg_blk, wg_row0;
+  for (int b = 0; b < nd.nblk; ++b) {
+    const int64_t sb = ndh.blk_off[b + 1] - ndh.blk_off[b];
+    inv_off[b + 1] = inv_off[b] + sb * sb;
+    for (int64_t r0 = 0; r0 < sb; r0 += 64) {
+      wg_blk.push_back(b);
+      wg_row0.push_back((int32_t)r0);
+    }
+  }
+  nd.nwg = (int32_t)wg_blk.size();
+  // row parts of the top product: about 2048 waves, at least 64 rows a part,
+  // at most what the kernels keep in LDS
+  const int64_t cap = nd_max_rows(d.max_nrhs);
+  if (nd.R > 0) {
+    const int64_t nrb = nd.ldC / 64;
+    int64_t P = std::max<int64_t>(1, std::min<int64_t>((2048 + nrb - 1) / nrb, (nd.R + 63) / 64));
+    int64_t per = (nd.R + P - 1) / P;
+    if (per > cap) {
+      P = (nd.R + cap - 1) / cap;
+      per = (nd.R + P - 1) / P;
+    }
+    nd.P = (int32_t)P;
+    nd.per = (int32_t)per;
+  }
+  std::vector<int32_t> ord(ndh.order.begin(), ndh.order.end());
+  std::vector<int32_t> t_pos(ndh.t_pos.begin(), ndh.t_pos.end());
+  std::vector<int32_t> b_top(ndh.b_top.begin(), ndh.b_top.end());
+  std::vector<int32_t> t_ri(t_pos.size()), t_ci(t_pos.size()), b_ri(b_top.size()), b_ci(b_top.size());
+  for (int64_t t = 0; t < ndh.ntop; ++t)
+    for (int64_t q = ndh.t_ptr[t]; q < ndh.t_ptr[t + 1]; ++q) {
+      t_ri[q] = ord[nd.nrows + t];
+      t_ci[q] = ord[ndh.t_pos[q]];
+    }
+  for (int64_t r = 0; r < nd.nrows; ++r)
+    for (int64_t q = ndh.b_ptr[r]; q < ndh.b_ptr[r + 1]; ++q) {
+      b_ri[q] = ord[r];
+      b_ci[q] = ord[nd.nrows + ndh.b_top[q]];
+    }
+  nd.nt_pairs = (int64_t)t_pos.size();
+  nd.nb_pairs = (int64_t)b_top.size();
+  hipError_t e;
+#define NDUP(p, v)                              \
+  if ((e = upload(al, &(p), (v), sm)) != hipSuccess) return e
+  NDUP(nd.ord, ord);
+  NDUP(nd.src, nd.h_src);
+  NDUP(nd.blk_off, ndh.blk_off);
+  NDUP(nd.pad_off, ndh.pad_off);
+  NDUP(nd.inv_off, inv_off);
+  NDUP(nd.wg_blk, wg_blk);
+  NDUP(nd.wg_row0, wg_row0);
+  NDUP(nd.t_ptr, ndh.t_ptr);
+  NDUP(nd.t_pos, t_pos);
+  NDUP(nd.t_ri, t_ri);
+  NDUP(nd.t_ci, t_ci);
+  NDUP(nd.b_ptr, ndh.b_ptr);
+  NDUP(nd.b_top, b_top);
+  NDUP(nd.b_ri, b_ri);
+  NDUP(nd.b_ci, b_ci);
+#undef NDUP
+  const int NR = d.max_nrhs;
+  if ((e = dalloc(al, &nd.binv, (size_t)inv_off[nd.nblk])) != hipSuccess) return e;
+  if ((e = dalloc(al, &nd.cinv, (size_t)nd.R * nd.ldC)) != hipSuccess) return e;
+  if ((e = dalloc(al, &nd.t_val, (size_t)nd.nt_pairs)) != hipSuccess) return e;
+  if ((e = dalloc(al, &nd.b_val, (size_t)nd.nb_pairs)) != hipSuccess) return e;
+  if ((e = dalloc(al, &nd.y1, (size_t)std::max<int64_t>(nd.nrows, 1) * NR)) != hipSuccess) return e;
+  if ((e = dalloc(al, &nd.eta2, (size_t)std::max<int32_t>(nd.R, 1) * NR)) != hipSuccess) return e;
+  if ((e = dalloc(al, &nd.ypart, (size_t)nd.P * std::max<int32_t>(nd.ldC, 1) * NR)) != hipSuccess) return e;
+  (void)NL;
+  nd.on = 1;
+  return hipSuccess;
+}
+
+// Interface factorization (Algorithm 1, last step), on the handle's S: the
+// explicit S^{-1} (dense form) or the nested-dissection blocks and C^{-1};
+// the temporaries are allocated and freed here.  Synchronizes `st`.
+static hipError_t interface_inverse(DeviceState& d, hipStream_t st) {
+  if (d.NL <= 0) return hipSuccess;
+  const int64_t ld = d.nd.on ? d.nd.ldp : d.ldS;
+  const size_t nS = (size_t)ld * ld;
+  const int64_t ptiles = trtri_part_tiles((int)(ld / 64));
+  double *L = nullptr, *Li = nullptr, *part = nullptr, *Sp = nullptr;
+  hipError_t he = hipMalloc((void**)&L, nS * sizeof(double));
+  if (he == hipSuccess) he = hipMalloc((void**)&Li, nS * sizeof(double));
+  if (he == hipSuccess && ptiles > 0) he = hipMalloc((void**)&part, (size_t)ptiles * 4096 * sizeof(double));
+  if (he == hipSuccess && d.nd.on) he = hipMalloc((void**)&Sp, nS * sizeof(double));
+  if (he == hipSuccess) he = d.nd.on ? nd_numeric(d, Sp, L, Li, part, st) : dense_cholesky_inverse(d, L, Li, part, st);
+  const hipError_t he2 = hipStreamSynchronize(st);
+  if (he == hipSuccess) he = he2;
+  hipFree(L);
+  hipFree(Li);
+  hipFree(part);
+  hipFree(Sp);
+  return he;
+}
+
+// row of S (original numbering) named by a failing pivot of the interface
+// factorization (the nested-dissection form factors a reordered, padded S)
+static int64_t iface_fail_row(const DeviceState& d, int32_t row) {
+  if (!d.nd.on || row < 0 || row >= (int32_t)d.nd.h_src.size()) return row;
+  return d.nd.h_src[row];
 }
 
 // plain: factor the diagonal blocks A_ii of the partition as they are (no
@@ -335,6 +475,15 @@ static am_status setup_impl(const am_csr* A, const int32_t* part, int32_t nparts
   if (opt.flags & AM_FLAG_SEPARATE_IFACE) d.fuse_eta = 0;
   for (int32_t s2 = 0; s2 < st.m; ++s2)
     d.max_np = std::max<int32_t>(d.max_np, (int32_t)(lp.roff[s2 + 1] - lp.roff[s2]));
+  // nested-dissection layout of S where eta is its own launches (the dense
+  // explicit S^{-1} stays available with AM_FLAG_DENSE_IFACE, and is the
+  // fall-back when no dissection depth fits the kernels)
+  IfaceND ndh;
+  bool use_nd = false;
+  if (!plain && !d.fuse_eta && d.NL > 0 && !(opt.flags & AM_FLAG_DENSE_IFACE)) {
+    std::string e2;
+    use_nd = build_iface_nd(st, nd_max_rows(d.max_nrhs), 1.15, ndh, e2) == AM_OK;
+  }
 
   auto hipfail = [&](hipError_t he, const char* what) {
     fail(h, he == hipErrorOutOfMemory ? AM_ERR_OOM : AM_ERR_HIP,
@@ -537,8 +686,13 @@ static am_status setup_impl(const am_csr* A, const int32_t* part, int32_t nparts
   SCHK(dalloc(al, &d.mbf, (size_t)mbf_off[st.m]));
   const size_t nS = (size_t)d.ldS * d.ldS;
   SCHK(dalloc(al, &d.S, nS));
-  SCHK(dalloc(al, &d.Sinv, nS));
-  if (!d.fuse_eta && NL > 0) {
+  if (use_nd) {
+    SCHK(nd_upload(d, ndh, sm));
+    SCHK(dalloc(al, &d.Sinv, (size_t)d.nd.ldp * d.nd.ldp));  // reordered S^{-1}
+  } else {
+    SCHK(dalloc(al, &d.Sinv, nS));
+  }
+  if (!d.fuse_eta && NL > 0 && !use_nd) {
     // enough (row block, part) waves to fill the chip, each part >= 64 rows
     const int64_t nrb = (NL + 63) / 64;
     d.op_parts = (int32_t)std::max<int64_t>(1, std::min<int64_t>({64, (8192 + nrb - 1) / nrb, NL / 64}));
@@ -584,25 +738,9 @@ static am_status setup_impl(const am_csr* A, const int32_t* part, int32_t nparts
   SCHK(launch_assemble_S(d, sm));
   mark("interface matrix S", sm);
   if (NL > 0) {
-    double *L = nullptr, *Li = nullptr, *part = nullptr;
-    const int64_t ptiles = trtri_part_tiles(d.ldS / 64);
-    SCHK(hipMalloc((void**)&L, nS * sizeof(double)));
-    hipError_t he = hipMalloc((void**)&Li, nS * sizeof(double));
-    if (he == hipSuccess && ptiles > 0)
-      he = hipMalloc((void**)&part, (size_t)ptiles * 4096 * sizeof(double));
-    if (he != hipSuccess) {
-      hipFree(L);
-      hipFree(Li);
-      return hipfail(he, "hipMalloc(interface inverse scratch)");
-    }
-    he = dense_cholesky_inverse(d, L, Li, part, sm);
-    hipError_t he2 = hipStreamSynchronize(sm);
-    hipFree(L);
-    hipFree(Li);
-    hipFree(part);
-    if (he != hipSuccess) return hipfail(he, "dense_cholesky_inverse");
-    if (he2 != hipSuccess) return hipfail(he2, "interface factorization");
-    mark("interface inverse", nullptr);
+    hipError_t he = interface_inverse(d, sm);
+    if (he != hipSuccess) return hipfail(he, "interface factorization");
+    mark(d.nd.on ? "interface blocks (dissection)" : "interface inverse", nullptr);
   }
   SCHK(hipStreamSynchronize(sm));
   int32_t fl[4];
@@ -613,7 +751,8 @@ static am_status setup_impl(const am_csr* A, const int32_t* part, int32_t nparts
     return bail(AM_ERR_NOT_SPD);
   }
   if (fl[2] >= 0) {
-    fail(h, AM_ERR_NOT_SPD, "interface matrix S not SPD at row " + std::to_string(fl[2]));
+    fail(h, AM_ERR_NOT_SPD,
+         "interface matrix S not SPD at row " + std::to_string(iface_fail_row(d, fl[2])));
     return bail(AM_ERR_NOT_SPD);
   }
   // free set-up only arrays: the row layout of the factor served the
@@ -886,20 +1025,7 @@ am_status algmortar_update_values(am_handle h, const am_csr* A, void* stream) {
   if (he == hipSuccess) he = launch_mbf(d, st);
   if (he == hipSuccess) he = launch_invert_diag(d, st);
   if (he == hipSuccess) he = launch_assemble_S(d, st);
-  if (he == hipSuccess && d.NL > 0) {
-    const size_t nS = (size_t)d.ldS * d.ldS;
-    const int64_t ptiles = trtri_part_tiles(d.ldS / 64);
-    double *L = nullptr, *Li = nullptr, *part = nullptr;
-    he = hipMalloc((void**)&L, nS * sizeof(double));
-    if (he == hipSuccess) he = hipMalloc((void**)&Li, nS * sizeof(double));
-    if (he == hipSuccess && ptiles > 0) he = hipMalloc((void**)&part, (size_t)ptiles * 4096 * sizeof(double));
-    if (he == hipSuccess) he = dense_cholesky_inverse(d, L, Li, part, st);
-    const hipError_t he2 = hipStreamSynchronize(st);
-    if (he == hipSuccess) he = he2;
-    hipFree(L);
-    hipFree(Li);
-    hipFree(part);
-  }
+  if (he == hipSuccess && d.NL > 0) he = interface_inverse(d, st);
   const hipError_t he3 = hipStreamSynchronize(st);
   if (he == hipSuccess) he = he3;
   hipFree(Lr);
@@ -911,7 +1037,8 @@ am_status algmortar_update_values(am_handle h, const am_csr* A, void* stream) {
     return fail(h, AM_ERR_NOT_SPD, "A_i not SPD: subdomain " + std::to_string(fl[0]) + " pivot " +
                                        std::to_string(fl[1]));
   if (fl[2] >= 0)
-    return fail(h, AM_ERR_NOT_SPD, "interface matrix S not SPD at row " + std::to_string(fl[2]));
+    return fail(h, AM_ERR_NOT_SPD,
+                "interface matrix S not SPD at row " + std::to_string(iface_fail_row(d, fl[2])));
   h->numeric_ok = true;
   return AM_OK;
 }
@@ -1050,18 +1177,26 @@ am_status algmortar_apply(am_handle h, const double* r, double* z, int32_t nrhs,
 // row-part sums (op_parts x ldS x nr); each piece starts on a 256-byte
 // boundary.  Returns the doubles needed.
 static int64_t static_layout(const DeviceState& d, int nr, double* base, double** r, double** z,
-                             double** bpart, double** eta, double** ypart) {
+                             double** bpart, double** eta, double** ypart, double** y1 = nullptr,
+                             double** eta2 = nullptr) {
   int64_t off = 0;
   auto take = [&](int64_t count, double** out) {
     if (out) *out = base ? base + off : nullptr;
     off += (count + 31) / 32 * 32;
   };
+  // (the dissection form: y_B, eta_T and its part sums)
   take(d.n * nr, r);
   take(d.n * nr, z);
   if (d.NL > 0) {
     take(2 * d.NL * nr, bpart);
     take((int64_t)d.ldS * nr, eta);
-    if (!d.fuse_eta) take((int64_t)d.op_parts * d.ldS * nr, ypart);
+    if (d.nd.on) {
+      take(std::max<int64_t>(d.nd.nrows, 1) * nr, y1);
+      take((int64_t)std::max<int32_t>(d.nd.R, 1) * nr, eta2);
+      take((int64_t)d.nd.P * std::max<int32_t>(d.nd.ldC, 1) * nr, ypart);
+    } else if (!d.fuse_eta) {
+      take((int64_t)d.op_parts * d.ldS * nr, ypart);
+    }
   }
   return off;
 }
@@ -1094,27 +1229,36 @@ am_status algmortar_apply_static(am_handle h, const double* r, double* z, int32_
     am_status ts = autotune_tiles(h, nr);
     if (ts != AM_OK) return ts;
   }
-  double *sr, *sz, *sb = nullptr, *se = nullptr, *sy = nullptr;
-  static_layout(d, nr, base, &sr, &sz, &sb, &se, &sy);
+  double *sr, *sz, *sb = nullptr, *se = nullptr, *sy = nullptr, *s1 = nullptr, *s2 = nullptr;
+  static_layout(d, nr, base, &sr, &sz, &sb, &se, &sy, &s1, &s2);
   // the launchers read the work buffers from the handle's state: point them
   // at the static scratch for this call and put the handle's own back after
   struct Swap {
     DeviceState& d;
-    double *r, *z, *bpart, *eta, *ypart;
+    double *r, *z, *bpart, *eta, *ypart, *y1, *eta2, *ndpart;
     ~Swap() {
       d.r = r;
       d.z = z;
       d.bpart = bpart;
       d.eta = eta;
       d.ypart = ypart;
+      d.nd.y1 = y1;
+      d.nd.eta2 = eta2;
+      d.nd.ypart = ndpart;
     }
-  } keep{d, d.r, d.z, d.bpart, d.eta, d.ypart};
+  } keep{d, d.r, d.z, d.bpart, d.eta, d.ypart, d.nd.y1, d.nd.eta2, d.nd.ypart};
   d.r = sr;
   d.z = sz;
   if (d.NL > 0) {
     d.bpart = sb;
     d.eta = se;
-    if (!d.fuse_eta) d.ypart = sy;
+    if (d.nd.on) {
+      d.nd.y1 = s1;
+      d.nd.eta2 = s2;
+      d.nd.ypart = sy;
+    } else if (!d.fuse_eta) {
+      d.ypart = sy;
+    }
   }
   // columns nrhs .. nr-1 of the padded block: zeros (the array keeps the last
   // call's contents)
@@ -1465,6 +1609,17 @@ am_status algmortar_export_interface(am_handle h, int32_t which, double* out) {
   DeviceState& d = h->d;
   if (d.NL == 0) return AM_OK;
   HCHK(hipSetDevice(d.device));
+  if (which == 1 && d.nd.on) {  // the reordered inverse of the dissection form
+    const int64_t ldp = d.nd.ldp;
+    std::vector<double> tmp((size_t)ldp * ldp);
+    HCHK(hipMemcpy(tmp.data(), d.Sinv, sizeof(double) * tmp.size(), hipMemcpyDeviceToHost));
+    std::vector<int64_t> pos((size_t)d.NL);
+    for (int64_t a = 0; a < ldp; ++a)
+      if (d.nd.h_src[a] >= 0) pos[d.nd.h_src[a]] = a;
+    for (int64_t i = 0; i < d.NL; ++i)
+      for (int64_t j = 0; j < d.NL; ++j) out[i * d.NL + j] = tmp[(size_t)pos[i] * ldp + pos[j]];
+    return AM_OK;
+  }
   const double* src = which == 0 ? d.S : d.Sinv;
   HCHK(hipMemcpy2D(out, sizeof(double) * d.NL, src, sizeof(double) * d.ldS, sizeof(double) * d.NL,
                    d.NL, hipMemcpyDeviceToHost));
@@ -1505,7 +1660,7 @@ am_status algmortar_time_kernel(am_handle h, int32_t kernel, int32_t nrhs, int32
     if (ts == AM_OK) ts = algmortar_time_kernel(h->bj, 0, nrhs, reps, avg_ms, bytes);
     return ts == AM_OK ? AM_OK : fail(h, ts, h->bj->err);
   }
-  if (kernel == 1 && (h->d.fuse_eta || h->d.ypart == nullptr))
+  if (kernel == 1 && (h->d.fuse_eta || (!h->d.nd.on && h->d.ypart == nullptr)))
     return fail(h, AM_ERR_ARG,
                 "the interface solve of this handle runs inside the local kernel (kernel 0)");
   DeviceState& d = h->d;
@@ -1526,6 +1681,20 @@ am_status algmortar_time_kernel(am_handle h, int32_t kernel, int32_t nrhs, int32
     // with the interface solve fused in, its operator S^{-1} (once) and the
     // interface partial right-hand sides
     if (d.fuse_eta) by += (double)d.NL * d.NL * 8.0 + 2.0 * d.NL * 8.0 * nr;
+  } else if (kernel == 1 && d.nd.on) {
+    // the block inverses (twice when there are top rows), C^{-1} once, the
+    // coupling values and indices, the slots (read by both block passes and
+    // the top product), y_B and the part sums written and read, eta
+    const NdDevice& nd = d.nd;
+    double blocks = 0.0;
+    for (int b = 0; b < nd.nblk; ++b) {
+      const double sb = (double)(nd.h_blk_off[b + 1] - nd.h_blk_off[b]);
+      blocks += sb * sb * 8.0;
+    }
+    by = (nd.R > 0 ? 2.0 : 1.0) * blocks + (double)nd.R * nd.ldC * 8.0 +
+         12.0 * (double)(nd.nt_pairs + nd.nb_pairs) + 3.0 * 2.0 * d.NL * 8.0 * nr +
+         2.0 * (double)nd.nrows * 8.0 * nr + 2.0 * (double)nd.P * nd.ldC * 8.0 * nr +
+         (double)d.NL * 8.0 * nr + 2.0 * nd.R * 8.0 * nr;
   } else if (kernel == 1) {
     // S^{-1} once, the interface slots, the part sums written and read, eta
     by = (double)d.NL * d.NL * 8.0 + 3.0 * d.NL * 8.0 * nr +

@@ -159,6 +159,57 @@ __device__ __forceinline__ bool all_done(const PcgShared* sh) {
   return *(volatile const int32_t*)&sh->all_done != 0;
 }
 
+// The PCG stop test of one iteration, in one wave: folds the ||r||^2
+// partials of the update launch (same order in every workgroup), and
+// workgroup 0 (lane 0, when `writer`) stores the column states and all_done.
+template <int NR>
+__device__ __forceinline__ bool stop_test(const double* __restrict__ pb, int npb, int init,
+                                          PcgScalars* sc, PcgShared* sh, bool writer = true) {
+  // one wave: fold the ||r||^2 partials in block order (same order in every
+  // workgroup); the scalars are loaded first, independently of the partials
+  const int lane = threadIdx.x & 63;
+  const int nrhs = sh->nrhs, maxit = sh->maxit;
+  PcgScalars S[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) S[k] = sc[k];
+  double rr[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) rr[k] = 0.0;
+  for (int b = lane; b < npb; b += 64)
+#pragma unroll
+    for (int k = 0; k < NR; ++k) rr[k] += pb[(size_t)b * NR + k];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) rr[k] = wave_sum(rr[k]);
+  int alld = 1;
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    if (k >= nrhs) continue;
+    int done = S[k].done, conv = S[k].conv, status = S[k].status;
+    double bb = S[k].bb;
+    if (!done) {
+      if (init) {
+        bb = rr[k];
+        if (bb == 0.0) done = conv = 1;
+      } else if (rr[k] <= S[k].tol2 * S[k].bb) {
+        done = conv = 1;
+      } else if (S[k].it >= maxit) {
+        done = 1;
+        status = AM_ERR_NO_CONVERGENCE;
+      }
+    }
+    alld &= done;
+    if (blockIdx.x == 0 && lane == 0 && writer) {
+      sc[k].rr = rr[k];
+      sc[k].bb = bb;
+      sc[k].done = done;
+      sc[k].conv = conv;
+      sc[k].status = status;
+    }
+  }
+  if (blockIdx.x == 0 && lane == 0 && writer) sh->all_done = alld;
+  return alld != 0;
+}
+
 // ---------------------------------------------------------------------------
 // Interface partial right-hand sides from r (not from pbar): for subdomain s
 // and slot q (basis function n = I_s[q]),

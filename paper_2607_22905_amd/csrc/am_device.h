@@ -56,6 +56,42 @@ struct Reduce {
   int max_blocks = 0;
 };
 
+// Nested-dissection interface solve (kernels_nd.hip, layout from
+// build_iface_nd): device arrays, owned through DeviceState::allocs.
+struct NdDevice {
+  int32_t on = 0;          // the interface solve uses this form
+  int32_t nblk = 0;
+  int64_t nrows = 0;       // rows in blocks
+  int32_t R = 0;           // top rows
+  int32_t ldC = 0;         // leading dimension of C^{-1} (R rounded up to 64)
+  int32_t ldp = 0;         // padded dimension of the reordered S
+  int32_t nwg = 0;         // workgroups of k_nd_blocks
+  int32_t P = 1, per = 1;  // row parts of k_nd_top and rows per part
+  int64_t nt_pairs = 0, nb_pairs = 0;
+  std::vector<int64_t> h_blk_off, h_pad_off;  // host copies
+  std::vector<int32_t> h_src;
+  int32_t* ord = nullptr;      // [NL] ND position -> basis function (top rows last)
+  int32_t* src = nullptr;      // [ldp] padded position -> basis function, -1 on padding
+  int64_t* blk_off = nullptr;  // [nblk+1]
+  int64_t* pad_off = nullptr;  // [nblk+1]
+  int64_t* inv_off = nullptr;  // [nblk+1] offsets of the block inverses (full squares)
+  int32_t* wg_blk = nullptr;   // [nwg] block of each workgroup ..
+  int32_t* wg_row0 = nullptr;  // .. and its first row
+  double* binv = nullptr;      // block inverses
+  double* cinv = nullptr;      // [R][ldC] C^{-1}
+  int64_t* t_ptr = nullptr;    // [R+1] top row -> couplings to block rows
+  int32_t* t_pos = nullptr;    //   ND positions of those rows
+  double* t_val = nullptr;     //   S values
+  int32_t *t_ri = nullptr, *t_ci = nullptr;  // (row, column) of each value in S (set-up)
+  int64_t* b_ptr = nullptr;    // [nrows+1] block row -> couplings to top rows
+  int32_t* b_top = nullptr;    //   top indices
+  double* b_val = nullptr;
+  int32_t *b_ri = nullptr, *b_ci = nullptr;
+  double* y1 = nullptr;        // [nrows][max_nrhs]
+  double* eta2 = nullptr;      // [R][max_nrhs]
+  double* ypart = nullptr;     // [P][ldC][max_nrhs]
+};
+
 struct DeviceState {
   int device = 0;
   int prec = AM_FP64;
@@ -119,6 +155,7 @@ struct DeviceState {
   double* Sinv = nullptr;        // [ldS * ldS]
   int32_t op_parts = 1;          // row parts of the interface product (k_iface_op)
   double* ypart = nullptr;       // [op_parts][ldS][max_nrhs] part sums of eta
+  NdDevice nd;                   // nested-dissection interface solve (nd.on)
 
   // work vectors in device order, row-interleaved [n][nrhs]
   double* x = nullptr;
@@ -174,6 +211,19 @@ hipError_t dense_cholesky_inverse(DeviceState& d, double* L, double* Linv, doubl
 // eta = S^{-1} b; in PCG mode (pcg != 0) the launch first applies the stop
 // test to the ||r||^2 partials (init: records ||b||^2)
 hipError_t launch_iface_gemv(DeviceState& d, int nrhs, int pcg, int init, hipStream_t s);
+// out = Li^T Li over a T x T tile block (Li lower triangular, leading
+// dimension ld; both pointers at the block's first entry)
+hipError_t launch_lauum(const double* Li, double* out, int ld, int T, hipStream_t s);
+
+// ---- launchers (kernels_nd.hip) ----
+// largest block (rows) the nested-dissection kernels take for nr_max columns
+int64_t nd_max_rows(int nr_max);
+// eta = S^{-1} b by the nested-dissection block elimination (same contract
+// as launch_iface_gemv)
+hipError_t launch_nd_solve(DeviceState& d, int nrhs, int pcg, int init, hipStream_t s);
+// set-up: block inverses, C^{-1} and coupling values from d.S (see kernels_nd.hip)
+hipError_t nd_numeric(DeviceState& d, double* Sp, double* L, double* Li, double* part,
+                      hipStream_t s);
 
 // ---- launchers (kernels_pcg.hip) ----
 hipError_t launch_permute_in(const int32_t* dperm, int64_t n, const double* src, int64_t ld,

@@ -101,4 +101,30 @@ struct LocalPlan {
 
 am_status plan_local(const HostCSR& A, const Structure& st, LocalPlan& lp, std::string& err);
 
+// Nested-dissection layout of the interface system (iface_nd.cpp): the basis
+// functions in an order where the first nrows form nblk mutually uncoupled
+// diagonal blocks of S and the last ntop are the separators above them.
+struct IfaceND {
+  int32_t depth = 0;              // dissection levels above the blocks
+  int32_t nblk = 0;
+  int64_t nrows = 0;              // rows in blocks
+  int64_t ntop = 0;               // separator ("top") rows
+  std::vector<int32_t> order;     // [NL] ND position -> basis function
+  std::vector<int64_t> blk_off;   // [nblk+1] ND positions of the blocks
+  std::vector<int64_t> pad_off;   // [nblk+1] positions with every block padded to 64 rows;
+                                  // pad_off[nblk] is where the top rows start
+  int64_t ld = 0;                 // padded dimension, a multiple of 64
+  std::vector<int64_t> t_ptr;     // [ntop+1] per top row ..
+  std::vector<int64_t> t_pos;     // .. the ND positions (< nrows) of the block rows it couples to
+  std::vector<int64_t> b_ptr;     // [nrows+1] per block row ..
+  std::vector<int64_t> b_top;     // .. the top indices (ND position - nrows) it couples to
+};
+
+// Builds the layout from the interface structure; blocks have at most
+// max_rows rows and the padded dimension is at most max_growth times that of
+// S (the depth minimises the bytes of one solve under these limits).
+// AM_ERR_UNSUPPORTED when no depth meets the limits.
+am_status build_iface_nd(const Structure& st, int64_t max_rows, double max_growth, IfaceND& nd,
+                         std::string& err);
+
 }  // namespace am

@@ -650,6 +650,12 @@ hipError_t dense_cholesky_inverse(DeviceState& d, double* L, double* Li, double*
   return hipGetLastError();
 }
 
+hipError_t launch_lauum(const double* Li, double* out, int ld, int T, hipStream_t st) {
+  if (T <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lauum, dim3(T, T), dim3(256), 0, st, Li, out, ld, T);
+  return hipGetLastError();
+}
+
 template <int NR>
 static void gemv_t(DeviceState& d, hipStream_t st, int pcg, int init) {
   const int nrb = (int)((d.NL + 63) / 64);
@@ -667,6 +673,7 @@ static void gemv_t(DeviceState& d, hipStream_t st, int pcg, int init) {
 
 hipError_t launch_iface_gemv(DeviceState& d, int nr, int pcg, int init, hipStream_t st) {
   if (d.NL == 0 && !pcg) return hipSuccess;
+  if (d.nd.on) return launch_nd_solve(d, nr, pcg, init, st);
   // the part sums exist only on handles whose interface solve is not fused
   // into the local kernel (with no interface, the launches only take the
   // stop decision and touch no part sums)

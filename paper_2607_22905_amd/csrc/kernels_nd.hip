@@ -1,0 +1,317 @@
+// Nested-dissection interface solve eta = S^{-1} b for gfx950 (the interface
+// solve of Algorithm 2; S is SPD, Corollary cor-schur-eta).
+//
+// The host layout (iface_nd.cpp) orders the basis functions so that the
+// first rows form mutually uncoupled diagonal blocks B of S and the last ones
+// are the separators T above them.  Block elimination then gives
+//   y_B   = S_BB^{-1} b_B                          k_nd_blocks, pass 0
+//   eta_T = C^{-1} (b_T - S_TB y_B)                 k_nd_top (row parts), k_nd_fold
+//   eta_B = S_BB^{-1} (b_B - S_BT eta_T)            k_nd_blocks, pass 1
+// where C = S_TT - S_TB S_BB^{-1} S_BT.  Every S_bb^{-1} and C^{-1} is held
+// explicitly (dense, exactly symmetric), so each step is a set of matrix
+// products with no dependent chain inside a launch.  In this order C^{-1} is
+// the T block of S^{-1}, and S_bb^{-1} = L_bb^{-T} L_bb^{-1} with L the
+// Cholesky factor of the reordered S (the blocks of L over B are those of
+// the uncoupled blocks).  Set-up therefore runs the tiled dense Cholesky and
+// triangular inverse of kernels_iface.hip once on the reordered S, padded
+// so that every block starts on a 64-row tile, and forms the block products
+// L_bb^{-T} L_bb^{-1} with the same tile kernel.
+//
+// Right-hand sides b_n = bpart[2n] + bpart[2n+1] (interface slots, see
+// bpart_sub); eta is written in the original basis-function order, [n][NR].
+#include <algorithm>
+
+#include "am_common.h"
+
+namespace am {
+
+// rows of a block (and of a part of the top rows) whose right-hand side a
+// workgroup keeps in LDS: just under 64 KB (two workgroups per CU)
+template <int NR> struct NdCap {
+  static constexpr int rows = (7936 / NR) < 4096 ? 7936 / NR : 4096;
+};
+
+int64_t nd_max_rows(int nr_max) {
+  switch (nr_max) {
+    case 1: return NdCap<1>::rows;
+    case 2: return NdCap<2>::rows;
+    case 4: return NdCap<4>::rows;
+    case 8: return NdCap<8>::rows;
+    default: return NdCap<16>::rows;
+  }
+}
+
+// Workgroup (block b, rows row0 .. row0 + 63 of it): the block's right-hand
+// side goes to LDS, then out[row] = sum_j Sbb^{-1}[j][row] rhs[j] (the
+// inverse is symmetric, so its row j stands for column j: one coalesced load
+// of 64 values per j), lane = row, the four waves taking a quarter of the j
+// each; their partial sums are added in wave order.  Pass 0 writes y_B (ND
+// order), pass 1 subtracts S_BT eta_T from the right-hand side first and
+// writes eta_B in the original order.
+template <int NR>
+__global__ __launch_bounds__(256) void k_nd_blocks(
+    int pass, const int32_t* __restrict__ wg_blk, const int32_t* __restrict__ wg_row0,
+    const int64_t* __restrict__ blk_off, const int64_t* __restrict__ inv_off,
+    const double* __restrict__ binv, const int32_t* __restrict__ ord,
+    const double* __restrict__ bpart, const int64_t* __restrict__ b_ptr,
+    const int32_t* __restrict__ b_top, const double* __restrict__ b_val,
+    const double* __restrict__ eta2, double* __restrict__ y1, double* __restrict__ eta, int pcg,
+    int init, const PcgShared* sh) {
+  constexpr int CAP = NdCap<NR>::rows;
+  static_assert(CAP >= 256, "the partial sums reuse the right-hand side buffer");
+  __shared__ double rhs[CAP * NR];
+  __shared__ int skip;
+  if (threadIdx.x == 0) skip = (pcg && !init && all_done(sh)) ? 1 : 0;
+  __syncthreads();
+  if (skip) return;  // uniform: one read for the whole workgroup
+  const int b = wg_blk[blockIdx.x];
+  const int row0 = wg_row0[blockIdx.x];
+  const int64_t o = blk_off[b];
+  const int s = (int)(blk_off[b + 1] - o);
+  const double* inv = binv + inv_off[b];
+  for (int t = threadIdx.x; t < s * NR; t += blockDim.x) {
+    const int j = t / NR, k = t % NR;
+    const int64_t n = ord[o + j];
+    double v = bpart[(size_t)(2 * n) * NR + k] + bpart[(size_t)(2 * n + 1) * NR + k];
+    if (pass)
+      for (int64_t q = b_ptr[o + j]; q < b_ptr[o + j + 1]; ++q)
+        v = fma(-b_val[q], eta2[(size_t)b_top[q] * NR + k], v);
+    rhs[t] = v;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int row = row0 + lane;
+  const int per = (s + 3) / 4;
+  const int jb = w * per, je = min(s, jb + per);
+  double acc[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) acc[k] = 0.0;
+  if (row < s) {
+    const double* col = inv + row;
+#pragma unroll 4
+    for (int j = jb; j < je; ++j) {
+      const double a = col[(size_t)j * s];
+#pragma unroll
+      for (int k = 0; k < NR; ++k) acc[k] = fma(a, rhs[j * NR + k], acc[k]);
+    }
+  }
+  __syncthreads();  // every wave is done with rhs
+  double* part = rhs;  // [4][64][NR]
+#pragma unroll
+  for (int k = 0; k < NR; ++k) part[(w * 64 + lane) * NR + k] = acc[k];
+  __syncthreads();
+  for (int t = threadIdx.x; t < 64 * NR; t += blockDim.x) {
+    const int l = t / NR, k = t % NR;
+    const int r = row0 + l;
+    if (r >= s) continue;
+    const double v = ((part[l * NR + k] + part[(64 + l) * NR + k]) + part[(128 + l) * NR + k]) +
+                     part[(192 + l) * NR + k];
+    if (pass == 0)
+      y1[(size_t)(o + r) * NR + k] = v;
+    else
+      eta[(size_t)ord[o + r] * NR + k] = v;
+  }
+}
+
+// Row parts of eta_T = C^{-1} r_T, r_T = b_T - S_TB y_B.  Workgroup
+// (part p, group g): the part's rows j of r_T are formed in LDS (each from its
+// couplings to block rows), then wave w of the group takes the 64 outputs
+// 64 (4 g + w) + lane and sums C^{-1}[j][.] r_T[j] over the part's j (C^{-1}
+// symmetric: one coalesced load per j, streamed once, non-temporal).  The
+// part sums go to ypart[p][row][k].
+template <int NR>
+__global__ __launch_bounds__(256) void k_nd_top(
+    int R, int ldC, const double* __restrict__ cinv, int P, int per, int nrb,
+    const int32_t* __restrict__ ord_top, const double* __restrict__ bpart,
+    const int64_t* __restrict__ t_ptr, const int32_t* __restrict__ t_pos,
+    const double* __restrict__ t_val, const double* __restrict__ y1, double* __restrict__ ypart,
+    int pcg, int init, const PcgShared* sh) {
+  constexpr int CAP = NdCap<NR>::rows;
+  __shared__ double r2[CAP * NR];
+  __shared__ int skip;
+  if (threadIdx.x == 0) skip = (pcg && !init && all_done(sh)) ? 1 : 0;
+  __syncthreads();
+  if (skip) return;
+  const int p = blockIdx.x % P, g = blockIdx.x / P;
+  const int jb = p * per, je = min(R, jb + per);
+  for (int t = threadIdx.x; t < (je - jb) * NR; t += blockDim.x) {
+    const int j = jb + t / NR, k = t % NR;
+    const int64_t n = ord_top[j];
+    double v = bpart[(size_t)(2 * n) * NR + k] + bpart[(size_t)(2 * n + 1) * NR + k];
+    for (int64_t q = t_ptr[j]; q < t_ptr[j + 1]; ++q)
+      v = fma(-t_val[q], y1[(size_t)t_pos[q] * NR + k], v);
+    r2[t] = v;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int rb = 4 * g + w;
+  if (rb >= nrb) return;
+  const int row = rb * 64 + lane;  // < ldC; C^{-1} has zero columns beyond R
+  const double* col = cinv + row;
+  double acc[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) acc[k] = 0.0;
+#pragma unroll 4
+  for (int j = jb; j < je; ++j) {
+    const double a = __builtin_nontemporal_load(col + (size_t)j * ldC);
+#pragma unroll
+    for (int k = 0; k < NR; ++k) acc[k] = fma(a, r2[(j - jb) * NR + k], acc[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < NR; ++k) ypart[((size_t)p * ldC + row) * NR + k] = acc[k];
+}
+
+// eta_T = sum of the part sums in part order, to eta2 (ND order, for pass 1)
+// and to eta (original order).  In PCG mode wave 0 of workgroup 0 first
+// takes the iteration's stop decision from the ||r||^2 partials of the update
+// launch (the launches after this one read its outcome).
+template <int NR>
+__global__ __launch_bounds__(256) void k_nd_fold(int R, int ldC, int P,
+                                                 const double* __restrict__ ypart,
+                                                 const int32_t* __restrict__ ord_top,
+                                                 double* __restrict__ eta2, double* __restrict__ eta,
+                                                 int pcg, int init, const double* __restrict__ pb,
+                                                 int npb, PcgScalars* sc, PcgShared* sh) {
+  if (pcg && !init && all_done(sh)) return;
+  if (pcg && blockIdx.x == 0 && threadIdx.x < 64) stop_test<NR>(pb, npb, init, sc, sh);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)R * NR) return;
+  const int64_t r = t / NR;
+  const int k = (int)(t % NR);
+  double v = 0.0;
+  for (int p = 0; p < P; ++p) v += ypart[((size_t)p * ldC + r) * NR + k];
+  eta2[r * NR + k] = v;
+  eta[(size_t)ord_top[r] * NR + k] = v;
+}
+
+template <int NR>
+static void nd_solve_t(DeviceState& d, hipStream_t st, int pcg, int init) {
+  const NdDevice& nd = d.nd;
+  if (nd.R > 0) {
+    am_launch(d, true, false, k_nd_blocks<NR>, dim3(nd.nwg), dim3(256), st, 0, nd.wg_blk,
+              nd.wg_row0, nd.blk_off, nd.inv_off, nd.binv, nd.ord, d.bpart, nd.b_ptr, nd.b_top,
+              nd.b_val, nd.eta2, nd.y1, d.eta, pcg, init, d.shared);
+    const int nrb = (nd.ldC + 63) / 64;
+    am_launch(d, false, false, k_nd_top<NR>, dim3(nd.P * ((nrb + 3) / 4)), dim3(256), st, nd.R,
+              nd.ldC, nd.cinv, nd.P, nd.per, nrb, nd.ord + nd.nrows, d.bpart, nd.t_ptr, nd.t_pos,
+              nd.t_val, nd.y1, nd.ypart, pcg, init, d.shared);
+  }
+  const unsigned nb = (unsigned)std::max<int64_t>(1, ((int64_t)nd.R * NR + 255) / 256);
+  am_launch(d, nd.R == 0, false, k_nd_fold<NR>, dim3(nb), dim3(256), st, nd.R, nd.ldC, nd.P,
+            nd.ypart, nd.ord + nd.nrows, nd.eta2, d.eta, pcg, init, d.red.pb, d.m, d.sc,
+            d.shared);
+  am_launch(d, false, true, k_nd_blocks<NR>, dim3(nd.nwg), dim3(256), st, 1, nd.wg_blk,
+            nd.wg_row0, nd.blk_off, nd.inv_off, nd.binv, nd.ord, d.bpart, nd.b_ptr, nd.b_top,
+            nd.b_val, nd.eta2, nd.y1, d.eta, pcg, init, d.shared);
+}
+
+hipError_t launch_nd_solve(DeviceState& d, int nr, int pcg, int init, hipStream_t st) {
+  if (nr > d.max_nrhs) return hipErrorInvalidValue;
+  switch (nr) {
+    case 1: nd_solve_t<1>(d, st, pcg, init); break;
+    case 2: nd_solve_t<2>(d, st, pcg, init); break;
+    case 4: nd_solve_t<4>(d, st, pcg, init); break;
+    case 8: nd_solve_t<8>(d, st, pcg, init); break;
+    case 16: nd_solve_t<16>(d, st, pcg, init); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ---- set-up ----------------------------------------------------------------
+
+// Sp[a][c] = S[src[a]][src[c]] over the padded ND order (src = -1: padding,
+// which holds the identity)
+__global__ __launch_bounds__(256) void k_nd_gather(const double* __restrict__ S, int ldS,
+                                                   const int32_t* __restrict__ src, int ldp,
+                                                   double* __restrict__ Sp) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)ldp * ldp) return;
+  const int a = (int)(t / ldp), c = (int)(t % ldp);
+  const int32_t sa = src[a], sc = src[c];
+  Sp[t] = (sa < 0 || sc < 0) ? (a == c ? 1.0 : 0.0) : S[(size_t)sa * ldS + sc];
+}
+
+// C^{-1}[j][c] = X[top0 + j][top0 + c] for c < R, 0 for R <= c < ldC
+__global__ __launch_bounds__(256) void k_nd_extract_top(const double* __restrict__ X, int ldp,
+                                                        int64_t top0, int R, int ldC,
+                                                        double* __restrict__ cinv) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)R * ldC) return;
+  const int64_t j = t / ldC, c = t % ldC;
+  cinv[t] = c < R ? X[(size_t)(top0 + j) * ldp + top0 + c] : 0.0;
+}
+
+// block b's inverse as a full square (leading dimension s_b) from the
+// diagonal block of X that starts at pad_off[b]
+__global__ __launch_bounds__(256) void k_nd_extract_blocks(const double* __restrict__ X, int ldp,
+                                                           const int64_t* __restrict__ pad_off,
+                                                           const int64_t* __restrict__ blk_off,
+                                                           const int64_t* __restrict__ inv_off,
+                                                           double* __restrict__ binv) {
+  const int b = blockIdx.y;
+  const int64_t s = blk_off[b + 1] - blk_off[b], po = pad_off[b];
+  double* out = binv + inv_off[b];
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < s * s;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t a = t / s, c = t % s;
+    out[t] = X[(size_t)(po + a) * ldp + po + c];
+  }
+}
+
+// out[q] = S[ri[q]][ci[q]]
+__global__ __launch_bounds__(256) void k_nd_pairs(const double* __restrict__ S, int ldS,
+                                                  const int32_t* __restrict__ ri,
+                                                  const int32_t* __restrict__ ci, int64_t cnt,
+                                                  double* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < cnt) out[t] = S[(size_t)ri[t] * ldS + ci[t]];
+}
+
+// The numeric part of the set-up, on the S of the handle (original order):
+// reorder, factor and invert (tiled, kernels_iface.hip), form the block
+// inverses and C^{-1}, gather the coupling values.  L, Li: ldp x ldp scratch,
+// Sp: ldp x ldp scratch, part: trtri_part_tiles(ldp / 64) tiles.  d.Sinv
+// receives the reordered S^{-1} (ld ldp).
+hipError_t nd_numeric(DeviceState& d, double* Sp, double* L, double* Li, double* part,
+                      hipStream_t st) {
+  NdDevice& nd = d.nd;
+  const int ldp = nd.ldp;
+  const int64_t tot = (int64_t)ldp * ldp;
+  hipLaunchKernelGGL(k_nd_gather, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, d.S,
+                     d.ldS, nd.src, ldp, Sp);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // the tiled factorization reads d.S with leading dimension d.ldS
+  double* S0 = d.S;
+  const int32_t ld0 = d.ldS;
+  d.S = Sp;
+  d.ldS = ldp;
+  e = dense_cholesky_inverse(d, L, Li, part, st);
+  d.S = S0;
+  d.ldS = ld0;
+  if (e != hipSuccess) return e;
+  // block products L_bb^{-T} L_bb^{-1} into the (now free) factor buffer
+  for (int b = 0; b < nd.nblk; ++b) {
+    const int64_t po = nd.h_pad_off[b];
+    const int T = (int)((nd.h_blk_off[b + 1] - nd.h_blk_off[b] + 63) / 64);
+    e = launch_lauum(Li + po * ldp + po, L + po * ldp + po, ldp, T, st);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_nd_extract_blocks, dim3(64, nd.nblk), dim3(256), 0, st, L, ldp, nd.pad_off,
+                     nd.blk_off, nd.inv_off, nd.binv);
+  if (nd.R > 0) {
+    const int64_t nc = (int64_t)nd.R * nd.ldC;
+    hipLaunchKernelGGL(k_nd_extract_top, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st,
+                       d.Sinv, ldp, nd.h_pad_off[nd.nblk], nd.R, nd.ldC, nd.cinv);
+  }
+  if (nd.nt_pairs > 0)
+    hipLaunchKernelGGL(k_nd_pairs, dim3((unsigned)((nd.nt_pairs + 255) / 256)), dim3(256), 0, st,
+                       d.S, d.ldS, nd.t_ri, nd.t_ci, nd.nt_pairs, nd.t_val);
+  if (nd.nb_pairs > 0)
+    hipLaunchKernelGGL(k_nd_pairs, dim3((unsigned)((nd.nb_pairs + 255) / 256)), dim3(256), 0, st,
+                       d.S, d.ldS, nd.b_ri, nd.b_ci, nd.nb_pairs, nd.b_val);
+  return hipGetLastError();
+}
+
+}  // namespace am

@@ -14,7 +14,7 @@ import numpy as np
 from . import _lib
 from ._lib import AmCsr, AmFaces, AmInfo, AmOptions, check, load
 
-__all__ = ["AlgMortar", "Tpfa", "partition_blocks", "partition_bisect", "structure",
+__all__ = ["AlgMortar", "Tpfa", "partition_blocks", "partition_bisect", "structure", "interface_nd",
            "structure_sizes"]
 
 
@@ -73,6 +73,21 @@ def structure_sizes(A, part, nparts, mortar="interface"):
     return nl.value, ne.value
 
 
+def interface_nd(A, part, nparts, max_nrhs=1):
+    """Host-only nested-dissection order of the interface system:
+    (order, blk_off, ntop) -- ND position -> basis function, the block
+    boundaries, the number of separator rows last in the order."""
+    NL, _ = structure_sizes(A, part, nparts)
+    s, keep = _csr(A)
+    p = _np(part, np.int32)
+    order = np.empty(NL, dtype=np.int32)
+    blk = np.empty(NL + 1, dtype=np.int64)
+    nb, nt = c_int32(), c_int64()
+    check(load().am_interface_nd(byref(s), _ptr(p), int(nparts), int(max_nrhs), _ptr(order),
+                                 _ptr(blk), byref(nb), byref(nt)))
+    return order, blk[:nb.value + 1].copy(), nt.value
+
+
 def structure(A, part, nparts, mortar="interface"):
     """Host-only interface structure (perm, sub_ptr, iface_ptr, iface_ij, edge_k, edge_l)."""
     NL, NE = structure_sizes(A, part, nparts, mortar)
@@ -114,14 +129,15 @@ class AlgMortar:
     """Handle of a set-up AlgMortar preconditioner (Algorithm 1) on one GPU."""
 
     def __init__(self, A, part, nparts, prec="fp64", mortar="interface", max_nrhs=1, device=0,
-                 graph=True, stream=None, separate_iface=False):
+                 graph=True, stream=None, separate_iface=False, dense_iface=False):
         lib = load()
         s, keep = _csr(A)
         p = _np(part, np.int32)
         opt = AmOptions(local_prec=_lib.PREC[prec], mortar=_lib.MORTAR[mortar],
                         max_nrhs=int(max_nrhs), device=int(device),
                         flags=(0 if graph else _lib.AM_FLAG_NO_GRAPH)
-                        | (_lib.AM_FLAG_SEPARATE_IFACE if separate_iface else 0))
+                        | (_lib.AM_FLAG_SEPARATE_IFACE if separate_iface else 0)
+                        | (_lib.AM_FLAG_DENSE_IFACE if dense_iface else 0))
         h = c_void_p()
         st = c_void_p(0) if stream is False else _stream(stream)
         check(lib.algmortar_setup(byref(s), _ptr(p), int(nparts), byref(opt), st, byref(h)))

@@ -352,17 +352,19 @@ def test_pcg_16_rhs_bisect(prec):
     h.close()
 
 
+@pytest.mark.parametrize("dense", [False, True])
 @pytest.mark.parametrize("name,max_nrhs", [("c1", 1), ("layered", 1), ("ragged3d", 2),
                                            ("bisect", 2), ("layered", 4), ("ragged3d", 16),
                                            ("bisect", 16)])
-def test_separate_interface_product_parity(name, max_nrhs):
+def test_separate_interface_product_parity(name, max_nrhs, dense):
     """The interface solve as its own launches instead of inside the local
-    kernel: row-part outer products of the symmetric S^{-1} (1-2 right-hand
+    kernel: the nested-dissection block elimination (the default), or
+    (dense) row-part outer products of the symmetric S^{-1} (1-2 right-hand
     sides) or the same product on the FP64 matrix cores (4-16), then the part
     sums in part order.  Apply within 1e-12 (on 2, 3 or 9 columns, i.e. the
     2-, 4- and 16-column layouts) and PCG within 1e-8 of the oracle."""
     A, part, m, b, ora = setup_case(name)
-    h = am.AlgMortar(A, part, m, separate_iface=True, max_nrhs=max_nrhs)
+    h = am.AlgMortar(A, part, m, separate_iface=True, max_nrhs=max_nrhs, dense_iface=dense)
     if max_nrhs >= 2:
         ncol = {2: 2, 4: 3, 16: 9}[max_nrhs]
         R = np.random.default_rng(8).standard_normal((ncol, A.n))
