@@ -232,6 +232,48 @@ def precision_forms(P, part, m, b, x64, args, v64, its64):
     return res
 
 
+def interface_forms(P, part, m, b, x64, args, v64, its64, separate):
+    """The interface solve in its other forms on the same workload, FP64,
+    each timed like the main run: the inexact solve (block-Jacobi PCG on S to
+    rtol 1e-2, at most 50 inner iterations, flexible outer PCG; Sec. 6, Sec. 7)
+    and, where the solve is its own launches, the dense explicit S^-1 product
+    in place of the nested-dissection blocks.  Solve rates, speedups over the
+    main run, iterations and the solution's relative L2 distance from it."""
+    import torch
+
+    import paper_2607_22905_amd as am
+    forms = {"inexact_rtol_1e-2": dict(inexact_iface=True)}
+    if separate:
+        forms["dense_explicit_inverse"] = dict(dense_iface=True)
+    res = {}
+    nrhs = P.nrhs
+    for name, kw in forms.items():
+        h = am.AlgMortar(P.A, part, m, graph=not args.no_graph, max_nrhs=nrhs, **kw)
+        x = torch.empty_like(b)
+        for _ in range(args.warmup):
+            h.pcg(b, P.tol, out=x)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, info, _ = h.pcg(b, P.tol, out=x)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        its = max(i["iterations"] for i in info)
+        v = args.steps * nrhs / el
+        res[name] = {"value": v, "unit": "solves/s", "speedup_vs_main": v / v64,
+                     "ms_per_step": el / args.steps * 1e3, "iterations": its,
+                     "iteration_change_vs_main": its - its64,
+                     "true_rel_res": max(i["true_rel_res"] for i in info),
+                     "rel_l2_vs_main_solution": float(torch.linalg.norm(x - x64) /
+                                                      torch.linalg.norm(x64))}
+        if separate or name.startswith("inexact"):
+            ms_, by_ = h.time_kernel("gemv", nrhs=nrhs, reps=5)
+            res[name]["interface_solve_replayed_us"] = ms_ * 1e3
+        log(f"bench: interface form {name}: {v:.1f} solves/s ({v / v64:.2f}x), {its} iterations")
+        h.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -241,7 +283,8 @@ def main():
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision-forms", action="store_true",
-                    help="skip the FP32 / BF16 local-factor solves of the FP64 run")
+                    help="skip the FP32 / BF16 local-factor solves and the other interface-solve "
+                         "forms of the FP64 run")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--theta", type=float, default=None,
                     help="contrast sweep K -> K^theta (c2, c6)")
@@ -397,6 +440,8 @@ def main():
     h.close()
     if args.prec == "fp64" and smooth is None and not args.no_precision_forms:
         out["precision_forms"] = precision_forms(P, part, m, b, x64, args, out["value"], its)
+        out["interface_forms"] = interface_forms(P, part, m, b, x64, args, out["value"], its,
+                                                 separate=prof["gemv"][1] > 0)
     if args.grad > 0:
         out["gradient"] = gradient_timing(P, part, m, args.grad)
     if not args.no_cpu_baseline:

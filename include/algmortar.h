@@ -98,6 +98,14 @@ typedef struct {
  * dissection order of the interfaces and of the Schur complement on the
  * separators above them; Sec. 4, Corollary cor-schur-eta) */
 #define AM_FLAG_DENSE_IFACE 4u
+/* solve the interface system inexactly, by PCG with a block-Jacobi
+ * preconditioner on S stopped at a relative residual (the iterative option of
+ * Sec. 6, used with tolerance 1e-2 in Sec. 7): zero initial guess, blocks of
+ * 64 consecutive basis functions (lexicographic (i, j) numbering) solved
+ * exactly; defaults rtol 1e-2 and at most 50 inner iterations, see
+ * algmortar_set_inexact.  The outer PCG then uses the flexible Polak-Ribiere
+ * beta (the preconditioner depends on its argument). */
+#define AM_FLAG_INEXACT_IFACE 8u
 
 typedef struct {
   int32_t iterations;  /* PCG iterations (matrix products) performed */
@@ -212,6 +220,14 @@ am_status algmortar_setup(const am_csr* A, const int32_t* part, int32_t nparts,
  * and local solves return AM_ERR_NOT_SPD until an update succeeds. */
 am_status algmortar_update_values(am_handle h, const am_csr* A, void* stream);
 
+/* Tolerance and iteration cap of the inexact interface solve of a handle set
+ * up with AM_FLAG_INEXACT_IFACE: the inner PCG stops when
+ * ||b - S eta||_2 <= rtol ||b||_2 (recursive residual) or after maxit
+ * iterations.  rtol in [0, 1) (0: always maxit iterations), maxit in
+ * [1, 1000].  The next algmortar_pcg captures its iteration graphs again.
+ * AM_ERR_ARG on other handles or values. */
+am_status algmortar_set_inexact(am_handle h, double rtol, int32_t maxit);
+
 /* Block-Jacobi pre- and post-smoothing around the AlgMortar correction
  * (Sec. 5.4).  After this call algmortar_apply and algmortar_pcg use
  *   z = 0;  nu times z += B^{-1} (r - A z);  z += Mcal^{-1} (r - A z);
@@ -251,7 +267,8 @@ am_status algmortar_apply(am_handle h, const double* r, double* z, int32_t nrhs,
  * Needs 2 n nr + 2 NL nr + ldS nr doubles (plus, where the interface solve
  * is its own launches, its part sums and, in the dissection form, the block
  * and separator vectors), nr = nrhs rounded up to a power of two; AM_ERR_ARG
- * when that exceeds the array.  AM_ERR_UNSUPPORTED while a smoother is set.  Its
+ * when that exceeds the array.  AM_ERR_UNSUPPORTED while a smoother is set
+ * and on handles with the inexact interface solve.  Its
  * first call for a right-hand-side count on a handle whose local-kernel
  * layout is not yet chosen runs the autotuner and synchronizes (call
  * algmortar_tile_choice first to keep it asynchronous).  Asynchronous on
@@ -320,7 +337,13 @@ am_status algmortar_time_kernel(am_handle h, int32_t kernel, int32_t nrhs, int32
  * handles whose timings chose differently can differ in the last bits; with
  * the environment variable ALGMORTAR_TILE=c, candidate c (clamped to the
  * list) is used without timing (us then holds zeros), which makes results
- * reproducible across handles and processes. */
+ * reproducible across handles and processes.  With
+ * ALGMORTAR_AUTOTUNE_CACHE=path, the choices are appended to that text file
+ * (one line per tuned case: a key of the handle's sizes, window buckets,
+ * factor precision, interface form and right-hand-side count, and the
+ * choice) and read back by later handles and processes, which then use the
+ * recorded layout without timing (us holds zeros): the same results as the
+ * process that timed it. */
 am_status algmortar_tile_choice(am_handle h, int32_t nrhs, int32_t* choice, int32_t* ncand,
                                 double* us);
 

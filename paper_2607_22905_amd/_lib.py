@@ -17,6 +17,7 @@ MORTAR = {"interface": 0, "edge": 1}
 AM_FLAG_NO_GRAPH = 1
 AM_FLAG_SEPARATE_IFACE = 2
 AM_FLAG_DENSE_IFACE = 4
+AM_FLAG_INEXACT_IFACE = 8
 
 
 class AmCsr(ctypes.Structure):
@@ -61,6 +62,7 @@ _SIGS = {
     "algmortar_apply_static": [c_void_p, c_void_p, c_void_p, c_int32, c_int64, c_void_p],
     "algmortar_local_solve": [c_void_p, c_void_p, c_void_p, c_void_p],
     "algmortar_set_smoother": [c_void_p, c_void_p, c_int32, c_int32, c_void_p],
+    "algmortar_set_inexact": [c_void_p, c_double, c_int32],
     "algmortar_update_values": [c_void_p, POINTER(AmCsr), c_void_p],
     "algmortar_pcg": [c_void_p, c_void_p, c_void_p, c_int32, c_int64, c_double, c_int32, c_void_p, c_void_p],
     "algmortar_interfaces": [c_void_p] * 7,

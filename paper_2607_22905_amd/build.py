@@ -29,6 +29,7 @@ SOURCES = [
     "kernels_local_bf16.hip",
     "kernels_iface.hip",
     "kernels_nd.hip",
+    "kernels_inexact.hip",
     "kernels_pcg.hip",
     "kernels_smooth.hip",
     "kernels_tpfa.hip",

@@ -278,18 +278,21 @@ static hipError_t nd_upload(DeviceState& d, const IfaceND& ndh, hipStream_t sm) 
   for (int b = 0; b < nd.nblk; ++b) {
     const int64_t sb = ndh.blk_off[b + 1] - ndh.blk_off[b];
     inv_off[b + 1] = inv_off[b] + sb * sb;
+    nd.smax = std::max(nd.smax, sb);
     for (int64_t r0 = 0; r0 < sb; r0 += 64) {
       wg_blk.push_back(b);
       wg_row0.push_back((int32_t)r0);
     }
   }
   nd.nwg = (int32_t)wg_blk.size();
-  // row parts of the top product: about 2048 waves, at least 64 rows a part,
-  // at most what the kernels keep in LDS
+  // row parts of the top product: about 2048 waves, at most what the
+  // kernels keep in LDS
   const int64_t cap = nd_max_rows(d.max_nrhs);
   if (nd.R > 0) {
-    const int64_t nrb = nd.ldC / 64;
-    int64_t P = std::max<int64_t>(1, std::min<int64_t>((2048 + nrb - 1) / nrb, (nd.R + 63) / 64));
+    // (parts of at least 16 rows with one or two right-hand sides, 64 with
+    // more: the part sums grow with the columns)
+    const int64_t nrb = nd.ldC / 64, minper = d.max_nrhs <= 2 ? 16 : 64;
+    int64_t P = std::max<int64_t>(1, std::min<int64_t>((2048 + nrb - 1) / nrb, (nd.R + minper - 1) / minper));
     int64_t per = (nd.R + P - 1) / P;
     if (per > cap) {
       P = (nd.R + cap - 1) / cap;
@@ -346,6 +349,60 @@ static hipError_t nd_upload(DeviceState& d, const IfaceND& ndh, hipStream_t sm) 
   return hipSuccess;
 }
 
+// Device arrays of the inexact interface solve: the ELL pattern of S (row n
+// couples to the basis functions of its two subdomains), the block layout,
+// the vectors and partials of the inner PCG.
+static hipError_t ix_upload(DeviceState& d, const Structure& st, hipStream_t sm) {
+  IxDevice& ix = d.ix;
+  std::vector<void*>& al = d.allocs;
+  const int64_t NL = d.NL;
+  std::vector<std::vector<int32_t>> rows((size_t)NL);
+  int32_t w = 1;
+  for (int64_t n = 0; n < NL; ++n) {
+    auto& v = rows[n];
+    for (int side = 0; side < 2; ++side) {
+      const int32_t sd = st.iface_ij[2 * n + side];
+      for (int64_t q = st.isub_ptr[sd]; q < st.isub_ptr[sd + 1]; ++q) v.push_back(st.isub_list[q]);
+    }
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+    w = std::max<int32_t>(w, (int32_t)v.size());
+  }
+  ix.w = w;
+  std::vector<int32_t> scol((size_t)w * NL);
+  std::vector<int8_t> pad((size_t)w * NL);
+  for (int64_t n = 0; n < NL; ++n)
+    for (int32_t e = 0; e < w; ++e) {
+      const bool real = e < (int32_t)rows[n].size();
+      scol[(size_t)e * NL + n] = real ? rows[n][e] : (int32_t)n;
+      pad[(size_t)e * NL + n] = real ? 0 : 1;
+    }
+  ix.nblk = (int32_t)((NL + ix.bs - 1) / ix.bs);
+  std::vector<int64_t> inv_off(ix.nblk + 1, 0);
+  for (int b = 0; b < ix.nblk; ++b) {
+    const int64_t sb = std::min<int64_t>(ix.bs, NL - (int64_t)b * ix.bs);
+    inv_off[b + 1] = inv_off[b] + sb * sb;
+  }
+  hipError_t e;
+  if ((e = upload(al, &ix.scol, scol, sm)) != hipSuccess) return e;
+  if ((e = upload(al, &ix.pad, pad, sm)) != hipSuccess) return e;
+  if ((e = upload(al, &ix.inv_off, inv_off, sm)) != hipSuccess) return e;
+  const int NR = d.max_nrhs;
+  if ((e = dalloc(al, &ix.sval, (size_t)w * NL)) != hipSuccess) return e;
+  if ((e = dalloc(al, &ix.binv, (size_t)inv_off[ix.nblk])) != hipSuccess) return e;
+  double** vecs[5] = {&ix.r, &ix.z, &ix.q, &ix.p[0], &ix.p[1]};
+  for (double** v : vecs) {
+    if ((e = dalloc(al, v, (size_t)NL * NR)) != hipSuccess) return e;
+    if ((e = launch_fill(*v, NL * NR, 0.0, sm)) != hipSuccess) return e;
+  }
+  if ((e = dalloc(al, &ix.pa, (size_t)ix.nblk * NR)) != hipSuccess) return e;
+  if ((e = dalloc(al, &ix.pb[0], (size_t)ix.nblk * 2 * NR)) != hipSuccess) return e;
+  if ((e = dalloc(al, &ix.pb[1], (size_t)ix.nblk * 2 * NR)) != hipSuccess) return e;
+  if ((e = dalloc(al, &ix.sc, kMaxNRHS)) != hipSuccess) return e;
+  ix.on = 1;
+  return hipSuccess;
+}
+
 // Interface factorization (Algorithm 1, last step), on the handle's S: the
 // explicit S^{-1} (dense form) or the nested-dissection blocks and C^{-1};
 // the temporaries are allocated and freed here.  Synchronizes `st`.
@@ -358,8 +415,11 @@ static hipError_t interface_inverse(DeviceState& d, hipStream_t st) {
   hipError_t he = hipMalloc((void**)&L, nS * sizeof(double));
   if (he == hipSuccess) he = hipMalloc((void**)&Li, nS * sizeof(double));
   if (he == hipSuccess && ptiles > 0) he = hipMalloc((void**)&part, (size_t)ptiles * 4096 * sizeof(double));
-  if (he == hipSuccess && d.nd.on) he = hipMalloc((void**)&Sp, nS * sizeof(double));
-  if (he == hipSuccess) he = d.nd.on ? nd_numeric(d, Sp, L, Li, part, st) : dense_cholesky_inverse(d, L, Li, part, st);
+  if (he == hipSuccess && (d.nd.on || d.ix.on)) he = hipMalloc((void**)&Sp, nS * sizeof(double));
+  if (he == hipSuccess)
+    he = d.nd.on   ? nd_numeric(d, Sp, L, Li, part, st)
+         : d.ix.on ? ix_numeric(d, Sp, L, Li, part, st)
+                   : dense_cholesky_inverse(d, L, Li, part, st);
   const hipError_t he2 = hipStreamSynchronize(st);
   if (he == hipSuccess) he = he2;
   hipFree(L);
@@ -472,7 +532,8 @@ static am_status setup_impl(const am_csr* A, const int32_t* part, int32_t nparts
   // the tile kernel folds the per-wave partial rows in its second tile buffer
   // (at least 8 KB for every factor precision and window)
   if ((int64_t)lp.max_ni * pow2_at_least(std::max(opt.max_nrhs, 1)) * 8 * 8 > 8192) d.fuse_eta = 0;
-  if (opt.flags & AM_FLAG_SEPARATE_IFACE) d.fuse_eta = 0;
+  if (opt.flags & (AM_FLAG_SEPARATE_IFACE | AM_FLAG_INEXACT_IFACE)) d.fuse_eta = 0;
+  const bool use_ix = !plain && d.NL > 0 && (opt.flags & AM_FLAG_INEXACT_IFACE);
   for (int32_t s2 = 0; s2 < st.m; ++s2)
     d.max_np = std::max<int32_t>(d.max_np, (int32_t)(lp.roff[s2 + 1] - lp.roff[s2]));
   // nested-dissection layout of S where eta is its own launches (the dense
@@ -480,7 +541,7 @@ static am_status setup_impl(const am_csr* A, const int32_t* part, int32_t nparts
   // fall-back when no dissection depth fits the kernels)
   IfaceND ndh;
   bool use_nd = false;
-  if (!plain && !d.fuse_eta && d.NL > 0 && !(opt.flags & AM_FLAG_DENSE_IFACE)) {
+  if (!plain && !d.fuse_eta && d.NL > 0 && !use_ix && !(opt.flags & AM_FLAG_DENSE_IFACE)) {
     std::string e2;
     use_nd = build_iface_nd(st, nd_max_rows(d.max_nrhs), 1.15, ndh, e2) == AM_OK;
   }
@@ -692,7 +753,8 @@ static am_status setup_impl(const am_csr* A, const int32_t* part, int32_t nparts
   } else {
     SCHK(dalloc(al, &d.Sinv, nS));
   }
-  if (!d.fuse_eta && NL > 0 && !use_nd) {
+  if (use_ix) SCHK(ix_upload(d, st, sm));
+  if (!d.fuse_eta && NL > 0 && !use_nd && !use_ix) {
     // enough (row block, part) waves to fill the chip, each part >= 64 rows
     const int64_t nrb = (NL + 63) / 64;
     d.op_parts = (int32_t)std::max<int64_t>(1, std::min<int64_t>({64, (8192 + nrb - 1) / nrb, NL / 64}));
@@ -808,6 +870,29 @@ static am_status autotune_tiles(am_handle h, int nr) {
     d.tile_cand[slot] = std::min(std::max(c, 0), nc - 1);
     return AM_OK;
   }
+  // ALGMORTAR_AUTOTUNE_CACHE=file keeps the choices across processes: a
+  // line "key choice" per tuned case, the key describing what the layouts
+  // are timed on (sizes, window buckets, factor precision, interface form,
+  // right-hand sides); a case found there is not timed again
+  const char* cache = std::getenv("ALGMORTAR_AUTOTUNE_CACHE");
+  std::string key;
+  if (cache && *cache) {
+    key = "n" + std::to_string(d.n) + "_m" + std::to_string(d.m) + "_nl" + std::to_string(d.NL) +
+          "_b" + std::to_string(d.bucket_sub[0].size()) + "x" + std::to_string(d.bucket_sub[1].size()) +
+          "_p" + std::to_string(d.prec) + "_f" + std::to_string(d.fuse_eta) + "_pl" +
+          std::to_string(d.plain) + "_nr" + std::to_string(nr) + "_c" + std::to_string(nc);
+    if (FILE* f = std::fopen(cache, "r")) {
+      char k[256];
+      int c = -1, found = -1;
+      while (std::fscanf(f, "%255s %d", k, &c) == 2)
+        if (key == k) found = c;  // the last entry of a key wins
+      std::fclose(f);
+      if (found >= 0 && found < nc) {
+        d.tile_cand[slot] = found;
+        return AM_OK;
+      }
+    }
+  }
   hipStream_t st = h->own;
   HCHK(launch_fill(d.r, d.n * nr, 0.0, st));
   HCHK(launch_fill(d.z, d.n * nr, 0.0, st));
@@ -833,6 +918,11 @@ static am_status autotune_tiles(am_handle h, int nr) {
     }
   }
   d.tile_cand[slot] = bc;
+  if (!key.empty())
+    if (FILE* f = std::fopen(cache, "a")) {
+      std::fprintf(f, "%s %d\n", key.c_str(), bc);
+      std::fclose(f);
+    }
   return AM_OK;
 }
 
@@ -1043,6 +1133,17 @@ am_status algmortar_update_values(am_handle h, const am_csr* A, void* stream) {
   return AM_OK;
 }
 
+am_status algmortar_set_inexact(am_handle h, double rtol, int32_t maxit) {
+  if (!h) return fail(nullptr, AM_ERR_ARG, "null handle");
+  if (!h->d.ix.on) return fail(h, AM_ERR_ARG, "the handle was not set up with AM_FLAG_INEXACT_IFACE");
+  if (!(rtol >= 0.0 && rtol < 1.0) || maxit < 1 || maxit > 1000)
+    return fail(h, AM_ERR_ARG, "rtol must be in [0, 1) and maxit in [1, 1000]");
+  h->d.ix.rtol = rtol;
+  h->d.ix.maxit = maxit;
+  h->d.graph_nrhs = 0;  // the captured chunks hold the old launch sequence
+  return AM_OK;
+}
+
 am_status algmortar_set_smoother(am_handle h, const int32_t* blocks, int32_t nblocks,
                                  int32_t steps, void* stream) {
   if (!h) return fail(nullptr, AM_ERR_ARG, "null handle");
@@ -1208,6 +1309,8 @@ am_status algmortar_apply_static(am_handle h, const double* r, double* z, int32_
   if (nrhs == 1) ld = h->d.n;
   if (h->sm.steps > 0)
     return fail(h, AM_ERR_UNSUPPORTED, "algmortar_apply_static does not cover block-Jacobi smoothing");
+  if (h->d.ix.on)
+    return fail(h, AM_ERR_UNSUPPORTED, "algmortar_apply_static does not cover the inexact interface solve");
   DeviceState& d = h->d;
   const int nr = pow2_at_least(nrhs);
   const int64_t need = static_layout(d, nr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
@@ -1409,7 +1512,10 @@ static am_status pcg_impl(am_handle h, const double* b, double* x, int32_t nrhs,
   HCHK(launch_fill(d.p[0], nv, 0.0, st));
   HCHK(launch_fill(d.p[1], nv, 0.0, st));
   HCHK(launch_fill(d.eta, (int64_t)std::max<int32_t>(d.ldS, 1) * nr, 0.0, st));
-  HCHK(launch_pcg_init(d, nr, tol, maxit, d.prec != AM_FP64 ? 1 : 0, st));
+  // the flexible beta where the preconditioner is not a fixed symmetric
+  // operator: reduced-precision factors, an interface solve stopped by a
+  // tolerance
+  HCHK(launch_pcg_init(d, nr, tol, maxit, (d.prec != AM_FP64 || d.ix.on) ? 1 : 0, st));
   if (smooth) {
     // Smoothed preconditioner (some 4 nu + 10 launches per apply): plain
     // launches, and the stop flag is read after each stop test so that no
@@ -1660,7 +1766,7 @@ am_status algmortar_time_kernel(am_handle h, int32_t kernel, int32_t nrhs, int32
     if (ts == AM_OK) ts = algmortar_time_kernel(h->bj, 0, nrhs, reps, avg_ms, bytes);
     return ts == AM_OK ? AM_OK : fail(h, ts, h->bj->err);
   }
-  if (kernel == 1 && (h->d.fuse_eta || (!h->d.nd.on && h->d.ypart == nullptr)))
+  if (kernel == 1 && (h->d.fuse_eta || (!h->d.nd.on && !h->d.ix.on && h->d.ypart == nullptr)))
     return fail(h, AM_ERR_ARG,
                 "the interface solve of this handle runs inside the local kernel (kernel 0)");
   DeviceState& d = h->d;
@@ -1695,6 +1801,18 @@ am_status algmortar_time_kernel(am_handle h, int32_t kernel, int32_t nrhs, int32
          12.0 * (double)(nd.nt_pairs + nd.nb_pairs) + 3.0 * 2.0 * d.NL * 8.0 * nr +
          2.0 * (double)nd.nrows * 8.0 * nr + 2.0 * (double)nd.P * nd.ldC * 8.0 * nr +
          (double)d.NL * 8.0 * nr + 2.0 * nd.R * 8.0 * nr;
+  } else if (kernel == 1 && d.ix.on) {
+    // the inexact solve at its iteration cap: the first pass (slots, block
+    // inverses, r, z, eta) and per inner iteration S (ELL values and
+    // columns), the block inverses and the vectors it reads and writes
+    const IxDevice& ix = d.ix;
+    double blocks = 0.0;
+    for (int b = 0; b < ix.nblk; ++b) {
+      const double sb = (double)std::min<int64_t>(ix.bs, d.NL - (int64_t)b * ix.bs);
+      blocks += sb * sb * 8.0;
+    }
+    const double vec = (double)d.NL * 8.0 * nr;
+    by = blocks + 5.0 * vec + ix.maxit * (12.0 * ix.w * d.NL + blocks + 9.0 * vec);
   } else if (kernel == 1) {
     // S^{-1} once, the interface slots, the part sums written and read, eta
     by = (double)d.NL * d.NL * 8.0 + 3.0 * d.NL * 8.0 * nr +

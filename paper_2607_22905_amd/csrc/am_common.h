@@ -16,17 +16,23 @@ namespace am {
 // separate event record).  Arguments are converted to the kernel's parameter
 // types, as the extended launch packs them as given.
 template <typename... KArgs, typename... Args>
-inline void am_launch(DeviceState& d, bool first, bool last, void (*kern)(KArgs...), dim3 grid,
-                      dim3 block, hipStream_t st, Args&&... args) {
+inline void am_launch_shm(DeviceState& d, bool first, bool last, void (*kern)(KArgs...), dim3 grid,
+                          dim3 block, size_t shmem, hipStream_t st, Args&&... args) {
   static_assert(sizeof...(KArgs) == sizeof...(Args), "argument count");
   hipEvent_t e0 = first ? d.prof_ev[0] : nullptr, e1 = last ? d.prof_ev[1] : nullptr;
   if (e0 || e1) {
-    hipExtLaunchKernelGGL(kern, grid, block, 0, st, e0, e1, 0, static_cast<KArgs>(args)...);
+    hipExtLaunchKernelGGL(kern, grid, block, shmem, st, e0, e1, 0, static_cast<KArgs>(args)...);
     if (e0) d.prof_used[0] = true;
     if (e1) d.prof_used[1] = true;
   } else {
-    hipLaunchKernelGGL(kern, grid, block, 0, st, static_cast<KArgs>(args)...);
+    hipLaunchKernelGGL(kern, grid, block, shmem, st, static_cast<KArgs>(args)...);
   }
+}
+// the same with no dynamic LDS
+template <typename... KArgs, typename... Args>
+inline void am_launch(DeviceState& d, bool first, bool last, void (*kern)(KArgs...), dim3 grid,
+                      dim3 block, hipStream_t st, Args&&... args) {
+  am_launch_shm(d, first, last, kern, grid, block, 0, st, static_cast<Args&&>(args)...);
 }
 
 typedef uint16_t bf16_t;
@@ -208,6 +214,44 @@ __device__ __forceinline__ bool stop_test(const double* __restrict__ pb, int npb
   }
   if (blockIdx.x == 0 && lane == 0 && writer) sh->all_done = alld;
   return alld != 0;
+}
+
+// The same stop test taken by a whole workgroup (every thread of it calls
+// this): the partials are folded by all its threads (reduce_partials, a
+// fixed order), thread 0 stores the column states and all_done.  lds holds
+// (blockDim.x / 64) NR doubles.
+template <int NR>
+__device__ __forceinline__ void stop_test_wg(const double* __restrict__ pb, int npb, int init,
+                                             PcgScalars* sc, PcgShared* sh, double* lds) {
+  const int nrhs = sh->nrhs, maxit = sh->maxit;
+  double rr[NR];
+  reduce_partials<NR>(rr, pb, (unsigned)npb, lds);
+  int alld = 1;
+  for (int k = 0; k < nrhs && k < NR; ++k) {
+    const PcgScalars S = sc[k];
+    int done = S.done, conv = S.conv, status = S.status;
+    double bb = S.bb;
+    if (!done) {
+      if (init) {
+        bb = rr[k];
+        if (bb == 0.0) done = conv = 1;
+      } else if (rr[k] <= S.tol2 * S.bb) {
+        done = conv = 1;
+      } else if (S.it >= maxit) {
+        done = 1;
+        status = AM_ERR_NO_CONVERGENCE;
+      }
+    }
+    alld &= done;
+    if (threadIdx.x == 0) {
+      sc[k].rr = rr[k];
+      sc[k].bb = bb;
+      sc[k].done = done;
+      sc[k].conv = conv;
+      sc[k].status = status;
+    }
+  }
+  if (threadIdx.x == 0) sh->all_done = alld;
 }
 
 // ---------------------------------------------------------------------------

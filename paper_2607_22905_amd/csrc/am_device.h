@@ -66,6 +66,7 @@ struct NdDevice {
   int32_t ldC = 0;         // leading dimension of C^{-1} (R rounded up to 64)
   int32_t ldp = 0;         // padded dimension of the reordered S
   int32_t nwg = 0;         // workgroups of k_nd_blocks
+  int64_t smax = 0;        // rows of the largest block
   int32_t P = 1, per = 1;  // row parts of k_nd_top and rows per part
   int64_t nt_pairs = 0, nb_pairs = 0;
   std::vector<int64_t> h_blk_off, h_pad_off;  // host copies
@@ -90,6 +91,35 @@ struct NdDevice {
   double* y1 = nullptr;        // [nrows][max_nrhs]
   double* eta2 = nullptr;      // [R][max_nrhs]
   double* ypart = nullptr;     // [P][ldC][max_nrhs]
+};
+
+// Inexact interface solve (kernels_inexact.hip): per-column state of the
+// inner PCG, by iteration parity where one launch reads what the next writes
+struct IxScalars {
+  double rzs[2];     // (r, z) of the inner iteration
+  double bb;         // ||b||^2
+  int32_t done[2];   // inner solve stopped
+  int32_t iters;     // inner iterations of the last solve
+  int32_t pad_;
+};
+
+struct IxDevice {
+  int32_t on = 0;
+  int32_t bs = 64;         // block-Jacobi block rows (multiple of 64, at most 256)
+  int32_t nblk = 0;
+  int32_t maxit = 50;
+  int32_t w = 0;           // ELL width of S
+  double rtol = 1e-2;
+  int64_t* inv_off = nullptr;  // [nblk+1]
+  double* binv = nullptr;      // block inverses, full squares
+  int32_t* scol = nullptr;     // [w][NL] ELL columns of S (padding: the row itself)
+  int8_t* pad = nullptr;       // [w][NL] 1 on padding entries
+  double* sval = nullptr;      // [w][NL]
+  double *r = nullptr, *z = nullptr, *q = nullptr;
+  double* p[2] = {nullptr, nullptr};
+  double* pa = nullptr;                 // [nblk][max_nrhs] (p, q) partials
+  double* pb[2] = {nullptr, nullptr};   // [nblk][2 max_nrhs] (r, z), (r, r) partials
+  IxScalars* sc = nullptr;              // [kMaxNRHS]
 };
 
 struct DeviceState {
@@ -156,6 +186,7 @@ struct DeviceState {
   int32_t op_parts = 1;          // row parts of the interface product (k_iface_op)
   double* ypart = nullptr;       // [op_parts][ldS][max_nrhs] part sums of eta
   NdDevice nd;                   // nested-dissection interface solve (nd.on)
+  IxDevice ix;                   // inexact interface solve (ix.on)
 
   // work vectors in device order, row-interleaved [n][nrhs]
   double* x = nullptr;
@@ -223,6 +254,13 @@ int64_t nd_max_rows(int nr_max);
 hipError_t launch_nd_solve(DeviceState& d, int nrhs, int pcg, int init, hipStream_t s);
 // set-up: block inverses, C^{-1} and coupling values from d.S (see kernels_nd.hip)
 hipError_t nd_numeric(DeviceState& d, double* Sp, double* L, double* Li, double* part,
+                      hipStream_t s);
+
+// ---- launchers (kernels_inexact.hip) ----
+// eta ~ S^{-1} b by block-Jacobi PCG (same contract as launch_iface_gemv)
+hipError_t launch_ix_solve(DeviceState& d, int nrhs, int pcg, int init, hipStream_t s);
+// set-up: block inverses and the ELL values of S (see kernels_inexact.hip)
+hipError_t ix_numeric(DeviceState& d, double* Sbd, double* L, double* Li, double* part,
                       hipStream_t s);
 
 // ---- launchers (kernels_pcg.hip) ----

@@ -674,6 +674,7 @@ static void gemv_t(DeviceState& d, hipStream_t st, int pcg, int init) {
 hipError_t launch_iface_gemv(DeviceState& d, int nr, int pcg, int init, hipStream_t st) {
   if (d.NL == 0 && !pcg) return hipSuccess;
   if (d.nd.on) return launch_nd_solve(d, nr, pcg, init, st);
+  if (d.ix.on) return launch_ix_solve(d, nr, pcg, init, st);
   // the part sums exist only on handles whose interface solve is not fused
   // into the local kernel (with no interface, the launches only take the
   // stop decision and touch no part sums)

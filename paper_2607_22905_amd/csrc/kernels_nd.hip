@@ -22,11 +22,12 @@
 #include <algorithm>
 
 #include "am_common.h"
+#include "iface_products.h"
 
 namespace am {
 
 // rows of a block (and of a part of the top rows) whose right-hand side a
-// workgroup keeps in LDS: just under 64 KB (two workgroups per CU)
+// workgroup keeps in LDS: at most 64 KB
 template <int NR> struct NdCap {
   static constexpr int rows = (7936 / NR) < 4096 ? 7936 / NR : 4096;
 };
@@ -42,70 +43,74 @@ int64_t nd_max_rows(int nr_max) {
 }
 
 // Workgroup (block b, rows row0 .. row0 + 63 of it): the block's right-hand
-// side goes to LDS, then out[row] = sum_j Sbb^{-1}[j][row] rhs[j] (the
-// inverse is symmetric, so its row j stands for column j: one coalesced load
-// of 64 values per j), lane = row, the four waves taking a quarter of the j
-// each; their partial sums are added in wave order.  Pass 0 writes y_B (ND
-// order), pass 1 subtracts S_BT eta_T from the right-hand side first and
-// writes eta_B in the original order.
+// side goes to LDS, then out = Sbb^{-1} rhs for those 64 rows, the four
+// waves taking a quarter of the block's columns each (nd_wave_product); their
+// partial sums are added in wave order.  Pass 0 writes y_B (ND order), pass 1
+// subtracts S_BT eta_T from the right-hand side first (or, with from_y1,
+// takes that right-hand side from y1, where k_nd_rb formed it) and writes
+// eta_B in the original order.  Dynamic LDS: max(rows of the largest block,
+// 256) NR doubles.
+template <int NR> struct NdWaves { static constexpr int v = NR <= 2 ? 8 : 4; };
+
 template <int NR>
-__global__ __launch_bounds__(256) void k_nd_blocks(
-    int pass, const int32_t* __restrict__ wg_blk, const int32_t* __restrict__ wg_row0,
-    const int64_t* __restrict__ blk_off, const int64_t* __restrict__ inv_off,
-    const double* __restrict__ binv, const int32_t* __restrict__ ord,
-    const double* __restrict__ bpart, const int64_t* __restrict__ b_ptr,
-    const int32_t* __restrict__ b_top, const double* __restrict__ b_val,
-    const double* __restrict__ eta2, double* __restrict__ y1, double* __restrict__ eta, int pcg,
-    int init, const PcgShared* sh) {
-  constexpr int CAP = NdCap<NR>::rows;
-  static_assert(CAP >= 256, "the partial sums reuse the right-hand side buffer");
-  __shared__ double rhs[CAP * NR];
+__global__ __launch_bounds__(64 * NdWaves<NR>::v) void k_nd_blocks(
+    int pass, int from_y1, int nwg, const int32_t* __restrict__ wg_blk,
+    const int32_t* __restrict__ wg_row0, const int64_t* __restrict__ blk_off,
+    const int64_t* __restrict__ inv_off, const double* __restrict__ binv,
+    const int32_t* __restrict__ ord, const double* __restrict__ bpart,
+    const int64_t* __restrict__ b_ptr, const int32_t* __restrict__ b_top,
+    const double* __restrict__ b_val, const double* __restrict__ eta2, double* __restrict__ y1,
+    double* __restrict__ eta, int pcg, int init, const double* __restrict__ opb, int npb,
+    PcgScalars* sc, PcgShared* sh) {
+  constexpr int NW = NdWaves<NR>::v;
+  extern __shared__ double rhs[];
   __shared__ int skip;
+  __shared__ double red[NW * NR];
   if (threadIdx.x == 0) skip = (pcg && !init && all_done(sh)) ? 1 : 0;
   __syncthreads();
   if (skip) return;  // uniform: one read for the whole workgroup
+  if ((int)blockIdx.x == nwg) {
+    // the extra workgroup of the first launch of the solve: the PCG stop
+    // decision, beside the products (the later launches read its outcome;
+    // the other workgroups of this launch may see it or not, which changes
+    // nothing but work that the stop makes unneeded)
+    stop_test_wg<NR>(opb, npb, init, sc, sh, red);
+    return;
+  }
   const int b = wg_blk[blockIdx.x];
   const int row0 = wg_row0[blockIdx.x];
   const int64_t o = blk_off[b];
   const int s = (int)(blk_off[b + 1] - o);
-  const double* inv = binv + inv_off[b];
-  for (int t = threadIdx.x; t < s * NR; t += blockDim.x) {
-    const int j = t / NR, k = t % NR;
-    const int64_t n = ord[o + j];
-    double v = bpart[(size_t)(2 * n) * NR + k] + bpart[(size_t)(2 * n + 1) * NR + k];
-    if (pass)
-      for (int64_t q = b_ptr[o + j]; q < b_ptr[o + j + 1]; ++q)
-        v = fma(-b_val[q], eta2[(size_t)b_top[q] * NR + k], v);
-    rhs[t] = v;
-  }
-  __syncthreads();
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int row = row0 + lane;
-  const int per = (s + 3) / 4;
-  const int jb = w * per, je = min(s, jb + per);
-  double acc[NR];
-#pragma unroll
-  for (int k = 0; k < NR; ++k) acc[k] = 0.0;
-  if (row < s) {
-    const double* col = inv + row;
-#pragma unroll 4
-    for (int j = jb; j < je; ++j) {
-      const double a = col[(size_t)j * s];
-#pragma unroll
-      for (int k = 0; k < NR; ++k) acc[k] = fma(a, rhs[j * NR + k], acc[k]);
+  if (from_y1) {  // pass 1: b_B - S_BT eta_T, formed by k_nd_rb
+    for (int t = threadIdx.x; t < s * NR; t += blockDim.x) rhs[t] = y1[(size_t)o * NR + t];
+  } else {
+    for (int t = threadIdx.x; t < s * NR; t += blockDim.x) {
+      const int j = t / NR, k = t % NR;
+      const int64_t n = ord[o + j];
+      double v = bpart[(size_t)(2 * n) * NR + k] + bpart[(size_t)(2 * n + 1) * NR + k];
+      if (pass)
+        for (int64_t q = b_ptr[o + j]; q < b_ptr[o + j + 1]; ++q)
+          v = fma(-b_val[q], eta2[(size_t)b_top[q] * NR + k], v);
+      rhs[t] = v;
     }
   }
+  __syncthreads();
+  const int w = threadIdx.x >> 6;
+  const int per = (s + NW - 1) / NW;
+  const int jb = min(s, w * per), je = min(s, jb + per);
+  nd_d4 acc[4];
+  nd_wave_product<NR, false>(binv + inv_off[b], s, row0, s, jb, je, rhs, 0, acc);
   __syncthreads();  // every wave is done with rhs
-  double* part = rhs;  // [4][64][NR]
-#pragma unroll
-  for (int k = 0; k < NR; ++k) part[(w * 64 + lane) * NR + k] = acc[k];
+  double* part = rhs;  // [NW][64][NR]
+  nd_wave_each<NR>(acc, [&](int l, int k, double v) { part[(w * 64 + l) * NR + k] = v; });
   __syncthreads();
   for (int t = threadIdx.x; t < 64 * NR; t += blockDim.x) {
     const int l = t / NR, k = t % NR;
     const int r = row0 + l;
     if (r >= s) continue;
-    const double v = ((part[l * NR + k] + part[(64 + l) * NR + k]) + part[(128 + l) * NR + k]) +
-                     part[(192 + l) * NR + k];
+    double v = part[l * NR + k];
+#pragma unroll
+    for (int u = 1; u < NW; ++u) v += part[(64 * u + l) * NR + k];
     if (pass == 0)
       y1[(size_t)(o + r) * NR + k] = v;
     else
@@ -116,64 +121,58 @@ __global__ __launch_bounds__(256) void k_nd_blocks(
 // Row parts of eta_T = C^{-1} r_T, r_T = b_T - S_TB y_B.  Workgroup
 // (part p, group g): the part's rows j of r_T are formed in LDS (each from its
 // couplings to block rows), then wave w of the group takes the 64 outputs
-// 64 (4 g + w) + lane and sums C^{-1}[j][.] r_T[j] over the part's j (C^{-1}
-// symmetric: one coalesced load per j, streamed once, non-temporal).  The
-// part sums go to ypart[p][row][k].
-template <int NR>
+// 64 (4 g + w) .. and sums over the part's j (nd_wave_product; C^{-1} is
+// streamed once, non-temporal).  The part sums go to ypart[p][row][k].
+// Dynamic LDS: rows per part times NR doubles.
+template <int NR, bool PRE>
 __global__ __launch_bounds__(256) void k_nd_top(
     int R, int ldC, const double* __restrict__ cinv, int P, int per, int nrb,
     const int32_t* __restrict__ ord_top, const double* __restrict__ bpart,
     const int64_t* __restrict__ t_ptr, const int32_t* __restrict__ t_pos,
-    const double* __restrict__ t_val, const double* __restrict__ y1, double* __restrict__ ypart,
-    int pcg, int init, const PcgShared* sh) {
-  constexpr int CAP = NdCap<NR>::rows;
-  __shared__ double r2[CAP * NR];
+    const double* __restrict__ t_val, const double* __restrict__ y1,
+    const double* __restrict__ eta2, double* __restrict__ ypart, int pcg, int init,
+    const PcgShared* sh) {
+  extern __shared__ double r2[];
   __shared__ int skip;
   if (threadIdx.x == 0) skip = (pcg && !init && all_done(sh)) ? 1 : 0;
   __syncthreads();
   if (skip) return;
   const int p = blockIdx.x % P, g = blockIdx.x / P;
-  const int jb = p * per, je = min(R, jb + per);
-  for (int t = threadIdx.x; t < (je - jb) * NR; t += blockDim.x) {
-    const int j = jb + t / NR, k = t % NR;
-    const int64_t n = ord_top[j];
-    double v = bpart[(size_t)(2 * n) * NR + k] + bpart[(size_t)(2 * n + 1) * NR + k];
-    for (int64_t q = t_ptr[j]; q < t_ptr[j + 1]; ++q)
-      v = fma(-t_val[q], y1[(size_t)t_pos[q] * NR + k], v);
-    r2[t] = v;
+  const int jb = min(R, p * per), je = min(R, jb + per);
+  const double* v = r2;  // the part's rows of r_T
+  int vbase = jb;
+  if (PRE) {  // formed by k_nd_rt (held in eta2 until k_nd_fold)
+    v = eta2;
+    vbase = 0;
+  } else {
+    for (int t = threadIdx.x; t < (je - jb) * NR; t += blockDim.x) {
+      const int j = jb + t / NR, k = t % NR;
+      const int64_t n = ord_top[j];
+      double x = bpart[(size_t)(2 * n) * NR + k] + bpart[(size_t)(2 * n + 1) * NR + k];
+      for (int64_t q = t_ptr[j]; q < t_ptr[j + 1]; ++q)
+        x = fma(-t_val[q], y1[(size_t)t_pos[q] * NR + k], x);
+      r2[t] = x;
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int w = threadIdx.x >> 6;
   const int rb = 4 * g + w;
   if (rb >= nrb) return;
-  const int row = rb * 64 + lane;  // < ldC; C^{-1} has zero columns beyond R
-  const double* col = cinv + row;
-  double acc[NR];
-#pragma unroll
-  for (int k = 0; k < NR; ++k) acc[k] = 0.0;
-#pragma unroll 4
-  for (int j = jb; j < je; ++j) {
-    const double a = __builtin_nontemporal_load(col + (size_t)j * ldC);
-#pragma unroll
-    for (int k = 0; k < NR; ++k) acc[k] = fma(a, r2[(j - jb) * NR + k], acc[k]);
-  }
-#pragma unroll
-  for (int k = 0; k < NR; ++k) ypart[((size_t)p * ldC + row) * NR + k] = acc[k];
+  nd_d4 acc[4];
+  nd_wave_product<NR, true>(cinv, ldC, 64 * rb, ldC, jb, je, v, vbase, acc);
+  double* out = ypart + (size_t)p * ldC * NR;
+  nd_wave_each<NR>(acc, [&](int l, int k, double v) { out[(size_t)(64 * rb + l) * NR + k] = v; });
 }
 
 // eta_T = sum of the part sums in part order, to eta2 (ND order, for pass 1)
-// and to eta (original order).  In PCG mode wave 0 of workgroup 0 first
-// takes the iteration's stop decision from the ||r||^2 partials of the update
-// launch (the launches after this one read its outcome).
+// and to eta (original order).
 template <int NR>
 __global__ __launch_bounds__(256) void k_nd_fold(int R, int ldC, int P,
                                                  const double* __restrict__ ypart,
                                                  const int32_t* __restrict__ ord_top,
                                                  double* __restrict__ eta2, double* __restrict__ eta,
-                                                 int pcg, int init, const double* __restrict__ pb,
-                                                 int npb, PcgScalars* sc, PcgShared* sh) {
+                                                 int pcg, int init, const PcgShared* sh) {
   if (pcg && !init && all_done(sh)) return;
-  if (pcg && blockIdx.x == 0 && threadIdx.x < 64) stop_test<NR>(pb, npb, init, sc, sh);
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)R * NR) return;
   const int64_t r = t / NR;
@@ -184,25 +183,94 @@ __global__ __launch_bounds__(256) void k_nd_fold(int R, int ldC, int P,
   eta[(size_t)ord_top[r] * NR + k] = v;
 }
 
+// r_T = b_T - S_TB y_B, one thread per (top row, column), into eta2 (which
+// holds eta_T only from k_nd_fold on)
+template <int NR>
+__global__ __launch_bounds__(256) void k_nd_rt(int R, const int32_t* __restrict__ ord_top,
+                                               const double* __restrict__ bpart,
+                                               const int64_t* __restrict__ t_ptr,
+                                               const int32_t* __restrict__ t_pos,
+                                               const double* __restrict__ t_val,
+                                               const double* __restrict__ y1,
+                                               double* __restrict__ rt, int pcg, int init,
+                                               const PcgShared* sh) {
+  if (pcg && !init && all_done(sh)) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)R * NR) return;
+  const int64_t j = t / NR;
+  const int k = (int)(t % NR);
+  const int64_t n = ord_top[j];
+  double x = bpart[(size_t)(2 * n) * NR + k] + bpart[(size_t)(2 * n + 1) * NR + k];
+  for (int64_t q = t_ptr[j]; q < t_ptr[j + 1]; ++q)
+    x = fma(-t_val[q], y1[(size_t)t_pos[q] * NR + k], x);
+  rt[t] = x;
+}
+
+// b_B - S_BT eta_T, one thread per (block row, column), into y1 (y_B is no
+// longer needed once r_T is formed)
+template <int NR>
+__global__ __launch_bounds__(256) void k_nd_rb(int64_t nrows, const int32_t* __restrict__ ord,
+                                               const double* __restrict__ bpart,
+                                               const int64_t* __restrict__ b_ptr,
+                                               const int32_t* __restrict__ b_top,
+                                               const double* __restrict__ b_val,
+                                               const double* __restrict__ eta2,
+                                               double* __restrict__ rb, int pcg, int init,
+                                               const PcgShared* sh) {
+  if (pcg && !init && all_done(sh)) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nrows * NR) return;
+  const int64_t j = t / NR;
+  const int k = (int)(t % NR);
+  const int64_t n = ord[j];
+  double x = bpart[(size_t)(2 * n) * NR + k] + bpart[(size_t)(2 * n + 1) * NR + k];
+  for (int64_t q = b_ptr[j]; q < b_ptr[j + 1]; ++q)
+    x = fma(-b_val[q], eta2[(size_t)b_top[q] * NR + k], x);
+  rb[t] = x;
+}
+
+// Launch sequence.  1-2 columns: four launches, the coupling terms formed in
+// the prologues of the top product and of the second block pass (few
+// couplings per row there, and no launch boundary to pay).  4-16 columns:
+// r_T and b_B - S_BT eta_T get launches of their own, so that the products
+// read them instead of each workgroup forming its share again.
 template <int NR>
 static void nd_solve_t(DeviceState& d, hipStream_t st, int pcg, int init) {
+  constexpr bool PRE = NR >= 4;
+  constexpr int NW = NdWaves<NR>::v;
   const NdDevice& nd = d.nd;
+  const size_t shb = (size_t)std::max<int64_t>(nd.smax, 64 * NW) * NR * sizeof(double);
+  // the PCG stop test rides in one extra workgroup of the first launch
+  const unsigned extra = pcg ? 1u : 0u;
   if (nd.R > 0) {
-    am_launch(d, true, false, k_nd_blocks<NR>, dim3(nd.nwg), dim3(256), st, 0, nd.wg_blk,
-              nd.wg_row0, nd.blk_off, nd.inv_off, nd.binv, nd.ord, d.bpart, nd.b_ptr, nd.b_top,
-              nd.b_val, nd.eta2, nd.y1, d.eta, pcg, init, d.shared);
+    am_launch_shm(d, true, false, k_nd_blocks<NR>, dim3(nd.nwg + extra), dim3(64 * NW), shb, st,
+                  0, 0, nd.nwg, nd.wg_blk, nd.wg_row0, nd.blk_off, nd.inv_off, nd.binv, nd.ord,
+                  d.bpart, nd.b_ptr, nd.b_top, nd.b_val, nd.eta2, nd.y1, d.eta, pcg, init,
+                  d.red.pb, d.m, d.sc, d.shared);
+    if (PRE)
+      am_launch(d, false, false, k_nd_rt<NR>, dim3((unsigned)((nd.R * NR + 255) / 256)),
+                dim3(256), st, nd.R, nd.ord + nd.nrows, d.bpart, nd.t_ptr, nd.t_pos, nd.t_val,
+                nd.y1, nd.eta2, pcg, init, d.shared);
     const int nrb = (nd.ldC + 63) / 64;
-    am_launch(d, false, false, k_nd_top<NR>, dim3(nd.P * ((nrb + 3) / 4)), dim3(256), st, nd.R,
-              nd.ldC, nd.cinv, nd.P, nd.per, nrb, nd.ord + nd.nrows, d.bpart, nd.t_ptr, nd.t_pos,
-              nd.t_val, nd.y1, nd.ypart, pcg, init, d.shared);
+    am_launch_shm(d, false, false, k_nd_top<NR, PRE>, dim3(nd.P * ((nrb + 3) / 4)), dim3(256),
+                  PRE ? 0 : (size_t)nd.per * NR * sizeof(double), st, nd.R, nd.ldC, nd.cinv, nd.P,
+                  nd.per, nrb, nd.ord + nd.nrows, d.bpart, nd.t_ptr, nd.t_pos, nd.t_val, nd.y1,
+                  nd.eta2, nd.ypart, pcg, init, d.shared);
   }
   const unsigned nb = (unsigned)std::max<int64_t>(1, ((int64_t)nd.R * NR + 255) / 256);
-  am_launch(d, nd.R == 0, false, k_nd_fold<NR>, dim3(nb), dim3(256), st, nd.R, nd.ldC, nd.P,
-            nd.ypart, nd.ord + nd.nrows, nd.eta2, d.eta, pcg, init, d.red.pb, d.m, d.sc,
-            d.shared);
-  am_launch(d, false, true, k_nd_blocks<NR>, dim3(nd.nwg), dim3(256), st, 1, nd.wg_blk,
-            nd.wg_row0, nd.blk_off, nd.inv_off, nd.binv, nd.ord, d.bpart, nd.b_ptr, nd.b_top,
-            nd.b_val, nd.eta2, nd.y1, d.eta, pcg, init, d.shared);
+  if (nd.R > 0)
+    am_launch(d, false, false, k_nd_fold<NR>, dim3(nb), dim3(256), st, nd.R, nd.ldC, nd.P,
+              nd.ypart, nd.ord + nd.nrows, nd.eta2, d.eta, pcg, init, d.shared);
+  if (PRE && nd.R > 0)
+    am_launch(d, false, false, k_nd_rb<NR>, dim3((unsigned)((nd.nrows * NR + 255) / 256)),
+              dim3(256), st, nd.nrows, nd.ord, d.bpart, nd.b_ptr, nd.b_top, nd.b_val, nd.eta2,
+              nd.y1, pcg, init, d.shared);
+  // with no top rows this is the only launch (it then carries the stop test)
+  const unsigned extra1 = nd.R > 0 ? 0u : extra;
+  am_launch_shm(d, nd.R == 0, true, k_nd_blocks<NR>, dim3(nd.nwg + extra1), dim3(64 * NW), shb,
+                st, 1, (PRE && nd.R > 0) ? 1 : 0, nd.nwg, nd.wg_blk, nd.wg_row0, nd.blk_off,
+                nd.inv_off, nd.binv, nd.ord, d.bpart, nd.b_ptr, nd.b_top, nd.b_val, nd.eta2, nd.y1,
+                d.eta, pcg, init, d.red.pb, d.m, d.sc, d.shared);
 }
 
 hipError_t launch_nd_solve(DeviceState& d, int nr, int pcg, int init, hipStream_t st) {

@@ -129,7 +129,8 @@ class AlgMortar:
     """Handle of a set-up AlgMortar preconditioner (Algorithm 1) on one GPU."""
 
     def __init__(self, A, part, nparts, prec="fp64", mortar="interface", max_nrhs=1, device=0,
-                 graph=True, stream=None, separate_iface=False, dense_iface=False):
+                 graph=True, stream=None, separate_iface=False, dense_iface=False,
+                 inexact_iface=False):
         lib = load()
         s, keep = _csr(A)
         p = _np(part, np.int32)
@@ -137,7 +138,8 @@ class AlgMortar:
                         max_nrhs=int(max_nrhs), device=int(device),
                         flags=(0 if graph else _lib.AM_FLAG_NO_GRAPH)
                         | (_lib.AM_FLAG_SEPARATE_IFACE if separate_iface else 0)
-                        | (_lib.AM_FLAG_DENSE_IFACE if dense_iface else 0))
+                        | (_lib.AM_FLAG_DENSE_IFACE if dense_iface else 0)
+                        | (_lib.AM_FLAG_INEXACT_IFACE if inexact_iface else 0))
         h = c_void_p()
         st = c_void_p(0) if stream is False else _stream(stream)
         check(lib.algmortar_setup(byref(s), _ptr(p), int(nparts), byref(opt), st, byref(h)))
@@ -186,6 +188,11 @@ class AlgMortar:
         check(load().algmortar_apply(self._h, c_void_p(r.data_ptr()), c_void_p(z.data_ptr()), k,
                                      self.n, _stream(stream)), self._h)
         return z
+
+    def set_inexact(self, rtol=1e-2, maxit=50):
+        """Tolerance and iteration cap of the inexact interface solve (handles
+        set up with inexact_iface=True)."""
+        check(load().algmortar_set_inexact(self._h, float(rtol), int(maxit)), self._h)
 
     def apply_static(self, r, out=None, stream=None):
         """The allocation-free form of ``apply``: the same result, with the

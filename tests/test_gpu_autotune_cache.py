@@ -1,0 +1,54 @@
+"""The autotuner's persisted choices (ALGMORTAR_AUTOTUNE_CACHE): two fresh
+processes solve the same 16-column system on the bisection grid (three
+candidate wave layouts); the first times the layouts and records its choice,
+the second reads it and times nothing; their solutions are equal bit for
+bit (the layouts differ in the order partial vectors are added, so without
+the record two processes could differ in the last bits)."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+SCRIPT = r'''
+import sys, json
+sys.path.insert(0, {root!r})
+import numpy as np, torch
+import paper_2607_22905_amd as am
+from tests.test_gpu_parity import _case
+A, part, m, b = _case("bisect")
+h = am.AlgMortar(A, part, m, max_nrhs=16)
+R = np.random.default_rng(5).standard_normal((16, A.n))
+X, info, _ = h.pcg(torch.as_tensor(R, device="cuda:0"), 1e-10)
+ch, us = h.tile_choice(16)
+np.save({out!r}, X.cpu().numpy())
+print(json.dumps({{"choice": ch, "us": us}}))
+h.close()
+'''
+
+
+def _run(tmp_path, tag, cache):
+    out = str(tmp_path / f"x_{tag}.npy")
+    env = dict(os.environ, ALGMORTAR_AUTOTUNE_CACHE=cache)
+    env.pop("ALGMORTAR_TILE", None)
+    r = subprocess.run([sys.executable, "-c", SCRIPT.format(root=ROOT, out=out)], env=env,
+                       capture_output=True, text=True, timeout=300, cwd=ROOT)
+    assert r.returncode == 0, r.stderr[-2000:]
+    import json
+    return np.load(out), json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def test_two_processes_bitwise_equal(tmp_path):
+    cache = str(tmp_path / "autotune.txt")
+    x1, i1 = _run(tmp_path, "first", cache)
+    lines = open(cache).read().split()
+    assert len(lines) >= 2 and int(lines[1]) == i1["choice"]
+    assert any(u > 0 for u in i1["us"])  # the first process timed the layouts
+    x2, i2 = _run(tmp_path, "second", cache)
+    assert i2["choice"] == i1["choice"] and all(u == 0 for u in i2["us"])
+    assert np.array_equal(x1, x2)
