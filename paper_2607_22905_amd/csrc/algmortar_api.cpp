@@ -781,6 +781,7 @@ static am_status setup_impl(const am_csr* A, const int32_t* part, int32_t nparts
   SCHK(dalloc(al, &d.red.pa, (size_t)d.red.spmv_blocks * kMaxNRHS));
   SCHK(dalloc(al, &d.red.pb, (size_t)st.m * kMaxNRHS));
   SCHK(dalloc(al, &d.red.pd, (size_t)st.m * 2 * kMaxNRHS));
+  SCHK(dalloc(al, &d.red.coef, 2 * kMaxNRHS));
   SCHK(dalloc(al, &d.red.counter, 8));
   SCHK(hipMemsetAsync(d.red.counter, 0, 8 * sizeof(unsigned), sm));
   SCHK(hipMemsetAsync(d.shared, 0, sizeof(PcgShared), sm));

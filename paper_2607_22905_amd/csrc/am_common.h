@@ -149,16 +149,15 @@ __device__ __forceinline__ void reduce_partials(double (&tot)[NR], const double*
   block_sum<NR>(tot, lds);
 }
 
-// Node vectors with NT right-hand sides are stored in groups of KG columns:
-// value (row, k) at ((k / KG) * n + row) * KG + k % KG, KG = min(NT, 4).  For
-// NT <= 4 this is the row-interleaved layout row * NT + k; for more, a group
-// of four columns is contiguous over the rows (16-byte values per row), which
-// keeps the accesses of a workgroup that serves one group coalesced.
+// Node vectors with NT right-hand sides: value (row, k) at row * NT + k, the
+// NT columns of a row contiguous (a 128-byte line for 16 columns), so that a
+// gathered neighbour brings all its columns in one line.  Kernels give each
+// thread a group of KG = min(NT, 4) columns of a row; with more columns the
+// NT / KG threads of a row are neighbouring lanes.
 template <int NT> struct KGroup { static constexpr int v = NT <= 4 ? NT : 4; };
 template <int NT>
-__device__ __forceinline__ size_t vix(int64_t n, int64_t row, int k) {
-  constexpr int KG = KGroup<NT>::v;
-  return ((size_t)(k / KG) * n + row) * KG + (k % KG);
+__device__ __forceinline__ size_t vix(int64_t /*n*/, int64_t row, int k) {
+  return (size_t)row * NT + k;
 }
 
 __device__ __forceinline__ bool all_done(const PcgShared* sh) {

@@ -42,14 +42,16 @@ struct PcgShared {
   int32_t all_done;
 };
 
-// Per-block partial sums of the PCG dots.  The kernel that needs a scalar
-// folds the producer's partials itself, in block order, identically in every
-// workgroup (deterministic, no fences or atomics); workgroup 0 stores the
-// scalars for later launches.
+// Per-block partial sums of the PCG dots.  With up to four columns the
+// kernel that needs a scalar folds the producer's partials itself, in block
+// order, identically in every workgroup (deterministic, no fences or
+// atomics), and workgroup 0 stores the scalars for later launches; with 8-16
+// columns a one-workgroup-per-column launch folds them once into coef.
 struct Reduce {
   double* pa = nullptr;         // (p, Ap) per SpMV block          [spmv_blocks][NR]
   double* pb = nullptr;         // ||r||^2 per subdomain            [m][NR]
   double* pd = nullptr;         // (r, z), (q, z) per subdomain     [m][2 NR]
+  double* coef = nullptr;       // beta, alpha of 8-16 columns      [2][kMaxNRHS]
   double* partial = nullptr;    // true-residual partials
   unsigned* counter = nullptr;
   int spmv_blocks = 0;

@@ -5,12 +5,15 @@
 //              interface partial right-hand sides 1/4 phat^T r per (subdomain, slot)
 //   gemv     : stop test on ||r||; eta = S^{-1} b      (kernels_iface.hip)
 //   local    : z = A_i^{-1} r + sum eta_m phat^(m), (r, z), (q, z) (kernels_local.hip)
-// Scalars stay on the device.  A launch that needs a scalar folds the per-
-// block partial sums of the launch that produced them, in block order and
-// identically in every workgroup (deterministic, no fences, no atomics);
-// workgroup 0 stores the scalars.  Every launch returns at once when all
-// columns have stopped, so a captured chunk of iterations can run past
-// convergence harmlessly.
+// Scalars stay on the device.  With up to four columns a launch that needs a
+// scalar folds the per-block partial sums of the launch that produced them,
+// in block order and identically in every workgroup (deterministic, no
+// fences, no atomics), and workgroup 0 stores the scalars; with 8 or 16
+// columns a small launch before the SpMV and the update folds them once
+// (k_pcg_coef).  Every launch returns at once when all columns have stopped,
+// so a captured chunk of iterations can run past convergence harmlessly.
+#include <type_traits>
+
 #include "am_common.h"
 
 namespace am {
@@ -86,6 +89,7 @@ __global__ __launch_bounds__(256) void k_spmv_p(int64_t n, int w, const int32_t*
                                                 const double* __restrict__ pd, int npd,
                                                 double* __restrict__ pa, PcgScalars* sc,
                                                 PcgShared* sh, int parity) {
+  static_assert(NT <= 4, "8 and 16 columns: k_spmv_rows");
   constexpr int KG = KGroup<NT>::v, TR = NT / KG;
   __shared__ double lds[8 * KG];
   const int blk = blockIdx.x / TR, g = blockIdx.x % TR, k0 = g * KG;
@@ -312,6 +316,7 @@ __global__ __launch_bounds__(256) void k_update_xr(
     const int64_t* __restrict__ bdst, const double* __restrict__ p, const double* __restrict__ q,
     double* __restrict__ x, double* r, double* bpart, const double* __restrict__ pa, int npa,
     double* __restrict__ pb, PcgScalars* sc, PcgShared* sh, int init, int parity) {
+  static_assert(NT <= 4, "8 and 16 columns: k_update_rows");
   constexpr int KG = KGroup<NT>::v, TR = NT / KG;
   // two rows per thread cover a 512-cell subdomain in one pass with half the
   // registers of four (more workgroups resident where there are many)
@@ -483,6 +488,299 @@ __global__ __launch_bounds__(256) void k_update_xr(
     for (int k = 0; k < KG; ++k) pb[(size_t)s * NT + k0 + k] = rr[k];
 }
 
+// ---------------------------------------------------------------------------
+// 8 and 16 right-hand sides.  A row's NT values are contiguous (vix) and the
+// TR = NT / 4 threads of a row are neighbouring lanes, each with a group of
+// four columns: the lanes of a row load the same ELL entries (one request
+// per wave) and together one line of each vector per row and per gathered
+// neighbour, so the matrix, the basis functions and every vector line are
+// fetched once for all columns.
+
+// Workgroup sums of NT (8 or 16) columns held as groups of four per thread
+// (group g = threadIdx.x % (NT / 4)): the lanes of a group are summed with
+// shuffles, then the four waves in order; out[c] for c < NT.
+template <int NT>
+__device__ __forceinline__ void group_sum(double (&v)[4], double* lds, double* out) {
+  constexpr int TR = NT / 4;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int off = TR; off < 64; off <<= 1) v[k] += __shfl_xor(v[k], off, 64);
+  if (lane < TR)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) lds[wv * NT + lane * 4 + k] = v[k];
+  __syncthreads();
+  if (threadIdx.x < NT) {
+    const int c = threadIdx.x;
+    out[c] = ((lds[c] + lds[NT + c]) + lds[2 * NT + c]) + lds[3 * NT + c];
+  }
+}
+
+// The step coefficients of NT (8 or 16) columns, once per launch instead of
+// in every workgroup of the kernel that uses them: one workgroup per column
+// sums that column's partials (thread t the rows t, t + 1024, ... in order,
+// then the threads in wave order, the same on every run) and takes the
+// decision workgroup 0 takes for fewer columns.
+//   kind 0: beta from the (r, z), (q, z) partials of the preconditioner
+//           launch, part = [nb][2 NT]; coef[c] = beta (Fletcher-Reeves, or
+//           the flexible Polak-Ribiere form), 0 for a stopped column;
+//   kind 1: alpha = (r, z) / (p, A p) from the SpMV partials,
+//           part = [nb][NT]; coef[kMaxNRHS + c] = alpha, 0 for a stopped
+//           column; counts the iteration.
+// A breakdown ((r, z) or (p, A p) not positive) stops the column with
+// AM_ERR_BREAKDOWN and gives it coefficient 0.
+template <int NT>
+__global__ __launch_bounds__(1024) void k_pcg_coef(int kind, const double* __restrict__ part, int nb,
+                                                   double* __restrict__ coef, PcgScalars* sc,
+                                                   PcgShared* sh, int parity) {
+  __shared__ double lds[16 * 2];
+  if (*(volatile const int32_t*)&sh->all_done) return;  // uniform
+  const int c = blockIdx.x;
+  const int stride = kind == 0 ? 2 * NT : NT;
+  double v[2] = {0.0, 0.0};
+#pragma unroll 4
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    v[0] += part[(size_t)b * stride + c];
+    if (kind == 0) v[1] += part[(size_t)b * stride + NT + c];
+  }
+  block_sum<2>(v, lds);
+  if (threadIdx.x != 0) return;
+  PcgScalars& S = sc[c];
+  double cf = 0.0;
+  if (c < sh->nrhs && !S.done) {
+    if (kind == 0) {
+      const double rzn = v[0];
+      int done = 0;
+      if (!(rzn > 0.0))
+        done = 1;
+      else if (S.it > 0)
+        cf = sh->flexible ? -S.alpha * v[1] / S.rzv[1 - parity] : rzn / S.rzv[1 - parity];
+      S.rzv[parity] = rzn;
+      S.rz = rzn;
+      S.qz = v[1];
+      S.beta = cf;
+      if (done) {
+        S.done = 1;
+        S.status = AM_ERR_BREAKDOWN;
+      }
+    } else {
+      const double pq = v[0];
+      S.pq = pq;
+      if (!(pq > 0.0)) {
+        S.alpha = 0.0;
+        S.done = 1;
+        S.status = AM_ERR_BREAKDOWN;
+      } else {
+        cf = S.rzv[parity] / pq;
+        S.alpha = cf;
+        S.it = S.it + 1;
+      }
+    }
+  }
+  coef[(kind == 0 ? 0 : kMaxNRHS) + c] = cf;
+}
+
+// p_new = z + beta p_old, q = A p_new, (p, q) partials (as k_spmv_p), beta
+// from k_pcg_coef.
+template <int NT, int MAXW>
+__global__ __launch_bounds__(256) void k_spmv_rows(int64_t n, int w, const int32_t* __restrict__ ec,
+                                                   const double* __restrict__ ev,
+                                                   const double* __restrict__ z,
+                                                   const double* __restrict__ pold,
+                                                   double* __restrict__ pnew,
+                                                   double* __restrict__ q,
+                                                   const double* __restrict__ coef,
+                                                   double* __restrict__ pa, PcgShared* sh) {
+  constexpr int KG = 4, TR = NT / KG, RW = 256 / TR;  // rows per workgroup step
+  __shared__ double lds[4 * NT];
+  const int g = threadIdx.x % TR, k0 = g * KG, rsub = threadIdx.x / TR;
+  if (*(volatile const int32_t*)&sh->all_done) return;  // uniform
+  // rows in grid-stride steps: at any time the whole grid works on one
+  // window of rows, so the gathered neighbours are mostly in cache (one
+  // contiguous chunk per workgroup, contiguous per XCD, measured slower:
+  // 1024 separate streams through the vectors and the ELL columns)
+  const int64_t step = (int64_t)gridDim.x * RW;
+  int64_t i = (int64_t)blockIdx.x * RW + rsub;
+  double beta[KG];
+#pragma unroll
+  for (int k = 0; k < KG; ++k) beta[k] = coef[k0 + k];
+  double pq[KG];
+#pragma unroll
+  for (int k = 0; k < KG; ++k) pq[k] = 0.0;
+  for (; i < n; i += step) {
+    int32_t col[MAXW];
+    double v[MAXW];
+#pragma unroll
+    for (int c = 0; c < MAXW; ++c) {
+      col[c] = c < w ? ec[(int64_t)c * n + i] : 0;
+      v[c] = c < w ? ev[(int64_t)c * n + i] : 0.0;
+    }
+    double zi[KG], pi[KG];
+#pragma unroll
+    for (int k = 0; k < KG; ++k) {
+      zi[k] = z[(size_t)i * NT + k0 + k];
+      pi[k] = pold[(size_t)i * NT + k0 + k];
+    }
+    double acc[KG];
+#pragma unroll
+    for (int k = 0; k < KG; ++k) acc[k] = 0.0;
+#pragma unroll
+    for (int c = 0; c < MAXW; ++c) {
+      if (c >= w) break;
+      const size_t o = (size_t)col[c] * NT + k0;
+#pragma unroll
+      for (int k = 0; k < KG; ++k) acc[k] = fma(v[c], fma(beta[k], pold[o + k], z[o + k]), acc[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < KG; ++k) {
+      const double pn = fma(beta[k], pi[k], zi[k]);
+      pnew[(size_t)i * NT + k0 + k] = pn;
+      q[(size_t)i * NT + k0 + k] = acc[k];
+      pq[k] = fma(pn, acc[k], pq[k]);
+    }
+  }
+  group_sum<NT>(pq, lds, pa + (size_t)blockIdx.x * NT);
+}
+
+// x += alpha p, r -= alpha q, ||r||^2 partials and the interface partial
+// right-hand sides bpart[2n + side] = 1/4 phat^(n)_s . r_s (as k_update_xr),
+// one workgroup per subdomain for all NT (8 or 16) columns, alpha from
+// k_pcg_coef.  Lane l of a wave holds column l % 16 of row 4 j + l / 16 of its
+// row steps j: that is the B operand of v_mfma_f64_16x16x4f64 (lane l holds
+// B[l / 16][l % 16]), and with A = 16 slots of the subdomain's basis
+// functions at the same four rows (lane l holds A[l % 16][l / 16]) the slot
+// sums are accumulated from the updated r in registers (D[l / 16 + 4 v][l % 16]
+// in element v), one tile of 16 slots per accumulator.  Slots beyond
+// kTiles * 16 are formed afterwards from r re-read.  Every value of P and of
+// the four vectors is read once.
+template <int NT, bool INIT>
+__global__ __launch_bounds__(256) void k_update_rows(
+    int64_t n, const int64_t* __restrict__ sub_ptr, const int64_t* __restrict__ isub_ptr,
+    const int64_t* __restrict__ mbf_off, const double* __restrict__ mbf,
+    const int64_t* __restrict__ bdst, const double* __restrict__ p, const double* __restrict__ q,
+    double* __restrict__ x, double* r, double* bpart, const double* __restrict__ coef,
+    double* __restrict__ pb, PcgShared* sh) {
+  static_assert(NT == 8 || NT == 16, "k_update_rows: 8 or 16 columns");
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  constexpr int RS = 8;      // row steps of four rows per wave and pass
+  constexpr int kTiles = 2;  // tiles of 16 slots accumulated in registers
+  constexpr int PASS = 4 * 4 * RS;
+  __shared__ double part[4][16][16];  // [wave][slot][column]
+  __shared__ double lds_rr[4][16];
+  if (*(volatile const int32_t*)&sh->all_done) return;  // uniform
+  const int s = blockIdx.x, tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6, li = lane % 16, lk = lane / 16;
+  const bool colok = li < NT;
+  const int64_t base = sub_ptr[s];
+  const int N = (int)(sub_ptr[s + 1] - base);
+  const int64_t i0 = isub_ptr[s];
+  const int ns = (int)(isub_ptr[s + 1] - i0);
+  const int nreg = ns < 16 * kTiles ? (ns + 15) / 16 : kTiles;  // uniform
+  const double* P = mbf + mbf_off[s];
+  const double alpha = (INIT || !colok) ? 0.0 : coef[kMaxNRHS + li];
+  d4 acc[kTiles];
+#pragma unroll
+  for (int t = 0; t < kTiles; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+  double rr = 0.0;
+  // this subdomain's rows (uniform bases, 32-bit lane offsets from here on)
+  const size_t sb = (size_t)base * NT;
+  double* __restrict__ xs = x + sb;
+  double* rs = r + sb;
+  const double* __restrict__ ps = p + sb;
+  const double* __restrict__ qs = q + sb;
+  // loads use clamped indices (always in bounds) and zero what lies outside
+  const int lic = colok ? li : NT - 1;
+  int qo[kTiles];
+  bool qok[kTiles];
+#pragma unroll
+  for (int t = 0; t < kTiles; ++t) {
+    const int qq = 16 * t + li;
+    qok[t] = t < nreg && qq < ns;
+    qo[t] = (qok[t] ? qq : 0) * N;
+  }
+  for (int r0 = wv * 4 * RS; r0 < N; r0 += PASS) {  // uniform in the wave
+    double rv[RS], xv[RS], pv[RS], qv[RS], av[kTiles][RS];
+#pragma unroll
+    for (int j = 0; j < RS; ++j) {
+      const int row = r0 + 4 * j + lk;
+      const int o = min(row, N - 1) * NT + lic;
+      rv[j] = rs[o];
+      if (!INIT) {
+        xv[j] = xs[o];
+        pv[j] = ps[o];
+        qv[j] = qs[o];
+      }
+#pragma unroll
+      for (int t = 0; t < kTiles; ++t) av[t][j] = P[qo[t] + min(row, N - 1)];
+    }
+#pragma unroll
+    for (int j = 0; j < RS; ++j) {
+      const int row = r0 + 4 * j + lk;
+      const bool ok = row < N && colok;
+      const int o = row * NT + li;
+      double rn = rv[j];
+      if (!INIT) {
+        rn = fma(-alpha, qv[j], rn);
+        if (ok) {
+          xs[o] = fma(alpha, pv[j], xv[j]);
+          rs[o] = rn;
+        }
+      }
+      rn = ok ? rn : 0.0;
+      rr = fma(rn, rn, rr);
+#pragma unroll
+      for (int t = 0; t < kTiles; ++t)
+        if (t < nreg)
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(qok[t] ? av[t][j] : 0.0, rn, acc[t], 0, 0, 0);
+    }
+  }
+  // ||r||^2: lanes of one column, then the waves in order
+  rr += __shfl_xor(rr, 16, 64);
+  rr += __shfl_xor(rr, 32, 64);
+  if (lane < 16) lds_rr[wv][lane] = rr;
+  __syncthreads();
+  if (tid < NT) pb[(size_t)s * NT + tid] = ((lds_rr[0][tid] + lds_rr[1][tid]) + lds_rr[2][tid]) + lds_rr[3][tid];
+  // the register tiles: the four waves' partial products added in wave order
+  for (int t = 0; t < nreg; ++t) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) part[wv][lk + 4 * v][li] = acc[0][v];
+    __syncthreads();
+    {
+      const int qi = tid / 16, k = tid % 16;
+      if (16 * t + qi < ns && k < NT) {
+        const double sum = ((part[0][qi][k] + part[1][qi][k]) + part[2][qi][k]) + part[3][qi][k];
+        bpart[(size_t)bdst[i0 + 16 * t + qi] * NT + k] = 0.25 * sum;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u + 1 < kTiles; ++u) acc[u] = acc[u + 1];  // the next tile into acc[0]
+  }
+  // slots beyond the register tiles, from the updated r
+  for (int q0 = 16 * kTiles; q0 < ns; q0 += 16) {
+    d4 a4 = {0.0, 0.0, 0.0, 0.0};
+    const int qq = q0 + li;
+    for (int row0 = 4 * wv; row0 < N; row0 += 16) {
+      const int row = row0 + lk;
+      const double a = (row < N && qq < ns) ? P[(size_t)qq * N + row] : 0.0;
+      const double b = (row < N && colok) ? r[(size_t)(base + row) * NT + li] : 0.0;
+      a4 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, a4, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) part[wv][lk + 4 * v][li] = a4[v];
+    __syncthreads();
+    {
+      const int qi = tid / 16, k = tid % 16;
+      if (q0 + qi < ns && k < NT) {
+        const double sum = ((part[0][qi][k] + part[1][qi][k]) + part[2][qi][k]) + part[3][qi][k];
+        bpart[(size_t)bdst[i0 + q0 + qi] * NT + k] = 0.25 * sum;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // ||b - A x||^2 per column (device positions).
 template <int NR>
 __global__ __launch_bounds__(256) void k_true_res(int64_t n, int w, const int32_t* __restrict__ ec,
@@ -564,27 +862,30 @@ hipError_t launch_pcg_init(DeviceState& d, int nr, double tol, int maxit, int fl
   return hipGetLastError();
 }
 
-// Workgroups per column group of the SpMV launch (and so its (p, Ap)
-// partials per column).  Every workgroup folds all the (r, z) partials of
-// its group, and every update workgroup all the (p, Ap) partials, so more
-// workgroups per group repeat that traffic.  With several groups the kernel
-// holds 224 VGPRs (two waves per SIMD, 512 resident workgroups), and a grid
-// of spmv_blocks / 2 in all keeps every workgroup resident: at 16 RHS on
-// 1M rows this measured 379 us against 406 (spmv_blocks in all), 417
-// (spmv_blocks / 4) and 482 (spmv_blocks per group).  One group keeps
-// spmv_blocks: halving it cost 71 -> 100 us at 128^3.
+// SpMV workgroups (and so (p, Ap) partials per column): at most 1024, one
+// round of resident workgroups.  With up to four columns every workgroup of
+// the SpMV and update launches folds the partials it needs itself; with 8-16
+// columns k_pcg_coef folds them once per launch.
 template <int NR>
-static int spmv_group_blocks(const DeviceState& d) {
-  constexpr int TR = NR / KGroup<NR>::v;
-  return std::max(1, d.red.spmv_blocks / (TR > 1 ? 2 * TR : 1));
+static int spmv_grid(const DeviceState& d) {
+  return std::max(1, d.red.spmv_blocks);
 }
 
 static hipError_t update_xr(DeviceState& d, int nr, int parity, int init, hipStream_t s) {
   const double* pn = d.p[1 - parity];
-  AM_NR_SWITCH(nr, am_launch(d, true, true, k_update_xr<NR>, dim3(d.m * (NR / KGroup<NR>::v)), dim3(256), s, d.n, d.sub_ptr,
-                                      d.isub_ptr, d.mbf_off, d.mbf, d.bdst, pn, d.q, d.x, d.r,
-                                      d.bpart, d.red.pa, spmv_group_blocks<NR>(d), d.red.pb, d.sc,
-                                      d.shared, init, parity));
+  AM_NR_SWITCH(nr, if constexpr (NR >= 8) {
+    if (!init)
+      am_launch(d, true, false, k_pcg_coef<NR>, dim3(NR), dim3(1024), s, 1, d.red.pa,
+                spmv_grid<NR>(d), d.red.coef, d.sc, d.shared, parity);
+    auto kern = (init ? &k_update_rows<NR, true> : &k_update_rows<NR, false>);
+    am_launch(d, init != 0, true, kern, dim3(d.m), dim3(256), s, d.n, d.sub_ptr, d.isub_ptr,
+              d.mbf_off, d.mbf, d.bdst, pn, d.q, d.x, d.r, d.bpart, d.red.coef, d.red.pb,
+              d.shared);
+  } else {
+    am_launch(d, true, true, k_update_xr<NR>, dim3(d.m), dim3(256), s, d.n, d.sub_ptr,
+              d.isub_ptr, d.mbf_off, d.mbf, d.bdst, pn, d.q, d.x, d.r, d.bpart, d.red.pa,
+              spmv_grid<NR>(d), d.red.pb, d.sc, d.shared, init, parity);
+  });
   return hipGetLastError();
 }
 
@@ -605,15 +906,23 @@ hipError_t launch_pcg_rr0(DeviceState& d, int nr, hipStream_t s) {
 hipError_t launch_pcg_spmv(DeviceState& d, int nr, int parity, hipStream_t s) {
   const double* po = d.p[parity];
   double* pn = d.p[1 - parity];
-  if (d.ell_w <= 8) {
-    AM_NR_SWITCH(nr, am_launch(d, true, true, k_spmv_p<NR, 8>, dim3(spmv_group_blocks<NR>(d) * (NR / KGroup<NR>::v)), dim3(256), s,
-                                        d.n, d.ell_w, d.ell_col, d.ell_val, d.z, po, pn, d.q,
-                                        d.red.pd, d.m, d.red.pa, d.sc, d.shared, parity));
-  } else {
-    AM_NR_SWITCH(nr, am_launch(d, true, true, k_spmv_p<NR, 32>, dim3(spmv_group_blocks<NR>(d) * (NR / KGroup<NR>::v)), dim3(256), s,
-                                        d.n, d.ell_w, d.ell_col, d.ell_val, d.z, po, pn, d.q,
-                                        d.red.pd, d.m, d.red.pa, d.sc, d.shared, parity));
-  }
+  auto go = [&](auto maxw) -> hipError_t {
+    constexpr int MW = decltype(maxw)::value;
+    AM_NR_SWITCH(nr, if constexpr (NR >= 8) {
+      am_launch(d, true, false, k_pcg_coef<NR>, dim3(NR), dim3(1024), s, 0, d.red.pd, d.m,
+                d.red.coef, d.sc, d.shared, parity);
+      am_launch(d, false, true, k_spmv_rows<NR, MW>, dim3(spmv_grid<NR>(d)), dim3(256), s, d.n,
+                d.ell_w, d.ell_col, d.ell_val, d.z, po, pn, d.q, d.red.coef, d.red.pa, d.shared);
+    } else {
+      am_launch(d, true, true, k_spmv_p<NR, MW>, dim3(spmv_grid<NR>(d)), dim3(256), s, d.n,
+                d.ell_w, d.ell_col, d.ell_val, d.z, po, pn, d.q, d.red.pd, d.m, d.red.pa, d.sc,
+                d.shared, parity);
+    });
+    return hipSuccess;
+  };
+  hipError_t e = d.ell_w <= 8 ? go(std::integral_constant<int, 8>{})
+                              : go(std::integral_constant<int, 32>{});
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 
