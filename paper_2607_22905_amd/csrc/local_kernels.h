@@ -873,14 +873,18 @@ __global__ __launch_bounds__(64 * G * W) void k_localt(
     }
 }
 
-// Tile form for 16 right-hand sides on the FP64 matrix cores (FP64 factors,
-// window 64, interface solve done before the launch).  Each tile pass is a
-// dense 64 x 64 by 64 x 16 product, so the four waves of the workgroup each
-// take 16 rows of the output block and accumulate all 16 right-hand sides
-// with v_mfma_f64_16x16x4_f64 over the 64 columns: no partial sums cross
-// waves.  Lane l holds A[l % 16][l / 16], B[l / 16][l % 16] and
-// D[l / 16 + 4 v][l % 16] (v < 4).  The block vectors (64 rows x 16) live in
-// LDS (two buffers, pitch 17); the tiles are staged as in k_localt.
+// Tile form for 16 right-hand sides on the matrix cores (window 64, interface
+// solve done before the launch).  Each tile pass is a dense 64 x 64 by
+// 64 x 16 product, so the four waves of the workgroup each take 16 rows of
+// the output block and accumulate all 16 right-hand sides over the 64
+// columns: no partial sums cross waves.  FP64 factors use
+// v_mfma_f64_16x16x4f64; FP32 and BF16 factors (widened to FP32 when the
+// tile is staged) use v_mfma_f32_16x16x4f32 with FP32 block vectors, the
+// arithmetic of the vector-unit kernel for those factors.  Both take lane l's
+// operands as A[l % 16][l / 16] and B[l / 16][l % 16]; the FP64 result is
+// D[l / 16 + 4 v][l % 16], the FP32 one D[4 (l / 16) + v][l % 16] (v < 4).
+// The block vectors (64 rows x 16) live in LDS (two buffers, pitch 17); the
+// tiles are staged as in k_localt.
 //   forward  y_b = t_b + Nlow_b t_b,   out_b = dinv y_b,
 //            t_{b+1} = r_{b+1} - U_b y_b
 //   backward s_b = out_b - U_b^T x_{b+1},   x_b = s_b + Nlow_b^T s_b,
@@ -889,52 +893,72 @@ __global__ __launch_bounds__(64 * G * W) void k_localt(
 // block) and U_b its upper part with the diagonal (the coupling to block
 // b + 1).
 typedef double am_mf_d4 __attribute__((ext_vector_type(4)));
+typedef float am_mf_f4 __attribute__((ext_vector_type(4)));
 constexpr int kMfVP = 17;  // LDS pitch of a block-vector row (16 values + 1)
+template <typename AT> struct MfAcc;
+template <> struct MfAcc<double> {
+  using V = am_mf_d4;
+  // row of the 16 x 16 result held in element v of a lane with l / 16 = lk
+  static __device__ __forceinline__ int row(int lk, int v) { return lk + 4 * v; }
+};
+template <> struct MfAcc<float> {
+  using V = am_mf_f4;
+  static __device__ __forceinline__ int row(int lk, int v) { return 4 * lk + v; }
+};
+__device__ __forceinline__ am_mf_d4 mf4(double a, double b, am_mf_d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ am_mf_f4 mf4(float a, float b, am_mf_f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
 
 
 // acc += sum over the 64 columns of A[rows][col] B[col][.] for a 16-row strip:
 // the 16 operand pairs are read from LDS first, then four independent chains
 // of four products (columns 4 kk + lk with kk = c mod 4 in chain c) are
 // added in chain order.
-template <typename AF, typename BF>
-__device__ __forceinline__ am_mf_d4 mf_pass(am_mf_d4 acc, AF&& afn, BF&& bfn) {
-  am_mf_d4 c[4];
+template <typename V, typename AF, typename BF>
+__device__ __forceinline__ V mf_pass(V acc, AF&& afn, BF&& bfn) {
+  using AT = decltype(afn(0));
+  V c[4];
   c[0] = acc;
 #pragma unroll
-  for (int t = 1; t < 4; ++t) c[t] = am_mf_d4{0.0, 0.0, 0.0, 0.0};
+  for (int t = 1; t < 4; ++t) c[t] = V{0, 0, 0, 0};
 #pragma unroll
   for (int h = 0; h < 2; ++h) {  // two halves of 8 operand pairs (registers)
-    double a[8], b[8];
+    AT a[8], b[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       a[u] = afn(8 * h + u);
       b[u] = bfn(8 * h + u);
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
-      c[u % 4] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], c[u % 4], 0, 0, 0);
+    for (int u = 0; u < 8; ++u) c[u % 4] = mf4(a[u], b[u], c[u % 4]);
   }
   return (c[0] + c[1]) + (c[2] + c[3]);
 }
 
-template <int NT>
+template <typename FT, int NT>
 __global__ __launch_bounds__(256) void k_localt_mf(
     const int32_t* __restrict__ subs, const int64_t* __restrict__ sub_ptr,
     const int64_t* __restrict__ roff, const int64_t* __restrict__ fac_off,
-    const double* __restrict__ Lc, const double* __restrict__ dinv, const double* rin,
+    const FT* __restrict__ Lc, const typename AccT<FT>::T* __restrict__ dinv, const double* rin,
     double* out, int mode, const int64_t* __restrict__ isub_ptr,
     const int32_t* __restrict__ isub_list, const int64_t* __restrict__ mbf_off,
     const double* __restrict__ mbf, const double* __restrict__ eta, const double* __restrict__ qv,
     double* __restrict__ partial, unsigned blk_off, PcgShared* sh, int64_t nrows) {
   static_assert(NT == 16, "one 16-column matrix-core tile");
+  using AT = typename AccT<FT>::T;  // arithmetic type: FP64, else FP32
+  using V = typename MfAcc<AT>::V;
   constexpr int PITCH = 65;
   constexpr int CH = 64 * PITCH;
   constexpr int NTHR = 256;
-  constexpr int NLD = 64 * 64 / (2 * NTHR);  // 16-byte loads per thread per tile
+  constexpr int VEC = 16 / (int)sizeof(FT);       // factor elements per 16-byte load
+  constexpr int NLD = 64 * 64 / (VEC * NTHR);     // 16-byte loads per thread per tile
   constexpr int PD = 1;  // one tile ahead in registers (two workgroups per CU)
-  __shared__ double tile[CH];  // one buffer: two workgroups fit a CU
-  __shared__ double vb[2][64 * kMfVP];
-  __shared__ double eta_s[64 * NT];
+  __shared__ AT tile[CH];  // one buffer: two workgroups fit a CU
+  __shared__ AT vb[2][64 * kMfVP];
+  __shared__ AT eta_s[64 * NT];
   __shared__ double dots[4][2 * NT];
 
   const int s = subs[blockIdx.x];
@@ -943,8 +967,8 @@ __global__ __launch_bounds__(256) void k_localt_mf(
   const int64_t ro = roff[s];
   const int NP = (int)(roff[s + 1] - ro);
   const int NB = NP / 64;
-  const double* lc = Lc + fac_off[s];
-  const double* dv = dinv + ro;
+  const FT* lc = Lc + fac_off[s];
+  const AT* dv = dinv + ro;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane % 16, lk = lane / 16;
@@ -962,27 +986,27 @@ __global__ __launch_bounds__(256) void k_localt_mf(
   auto tile_store = [&](int slot) {
 #pragma unroll
     for (int u = 0; u < NLD; ++u) {
-      const int e0 = (u * NTHR + (int)threadIdx.x) * 2;  // column e0 / 64, rows e0 % 64 ..
-      double* dst = tile + (e0 / 64) * PITCH + (e0 % 64);
-      double v[2];
+      const int e0 = (u * NTHR + (int)threadIdx.x) * VEC;  // column e0 / 64, rows e0 % 64 ..
+      AT* dst = tile + (e0 / 64) * PITCH + (e0 % 64);
+      FT v[VEC];
       __builtin_memcpy(v, &pre[slot][u], 16);
-      dst[0] = v[0];
-      dst[1] = v[1];
+#pragma unroll
+      for (int t = 0; t < VEC; ++t) dst[t] = (AT)widen_lds(v[t]);
     }
   };
-  // rows of this lane's part of the D layout: 16 w + lk + 4 v
-  auto drow = [&](int v) { return 16 * w + lk + 4 * v; };
+  // rows of this lane's part of the D layout
+  auto drow = [&](int v) { return 16 * w + MfAcc<AT>::row(lk, v); };
 
   tile_load(0, 0);
   if (mode == 2 && all_done(sh)) return;
   for (int t = threadIdx.x; t < ns * NT; t += NTHR)
-    eta_s[t] = eta[(size_t)isub_list[i0 + t / NT] * NT + (t % NT)];
+    eta_s[t] = (AT)eta[(size_t)isub_list[i0 + t / NT] * NT + (t % NT)];
   tile_store(0);
   if (1 < NB) tile_load(1, 0);
   // t_0 = r of block 0
   for (int e = threadIdx.x; e < 64 * NT; e += NTHR) {
     const int row = e / NT, k = e % NT;
-    vb[0][row * kMfVP + k] = row < N ? rin[vi(row, k)] : 0.0;
+    vb[0][row * kMfVP + k] = row < N ? (AT)rin[vi(row, k)] : AT(0);
   }
   __syncthreads();
 
@@ -990,29 +1014,29 @@ __global__ __launch_bounds__(256) void k_localt_mf(
   auto fwd_body = [&](const int b, auto parc) {
     constexpr int par = decltype(parc)::v;  // b & 1
     const int j0 = 64 * b;
-    double rn[4], dvl[4];
+    AT rn[4], dvl[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = j0 + 64 + drow(v);
-      rn[v] = row < N ? rin[vi(row, li)] : 0.0;
+      rn[v] = row < N ? (AT)rin[vi(row, li)] : AT(0);
       dvl[v] = dv[j0 + drow(v)];
     }
-    const double* T = tile;
+    const AT* T = tile;
     // pass B: y = t + Nlow t
-    am_mf_d4 acc;
+    V acc;
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[v] = vb[0][drow(v) * kMfVP + li];
     {
       const int ii = 16 * w + li;
       acc = mf_pass(
-          acc, [&](int kk) { const int jj = 4 * kk + lk; return ii > jj ? T[jj * PITCH + ii] : 0.0; },
+          acc, [&](int kk) { const int jj = 4 * kk + lk; return ii > jj ? T[jj * PITCH + ii] : AT(0); },
           [&](int kk) { return vb[0][(4 * kk + lk) * kMfVP + li]; });
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       vb[1][drow(v) * kMfVP + li] = acc[v];
       const int row = j0 + drow(v);
-      if (row < N) out[vi(row, li)] = acc[v] * dvl[v];
+      if (row < N) out[vi(row, li)] = (double)(acc[v] * dvl[v]);
     }
     __syncthreads();
     // pass A: t_{b+1} = r_{b+1} - U y
@@ -1021,7 +1045,7 @@ __global__ __launch_bounds__(256) void k_localt_mf(
     {
       const int ii = 16 * w + li;
       acc = mf_pass(
-          acc, [&](int kk) { const int jj = 4 * kk + lk; return ii <= jj ? -T[jj * PITCH + ii] : 0.0; },
+          acc, [&](int kk) { const int jj = 4 * kk + lk; return ii <= jj ? -T[jj * PITCH + ii] : AT(0); },
           [&](int kk) { return vb[1][(4 * kk + lk) * kMfVP + li]; });
     }
 #pragma unroll
@@ -1041,19 +1065,20 @@ __global__ __launch_bounds__(256) void k_localt_mf(
   // ---- backward sweep: tile NB-1 is still in LDS ----
   if (NB > 1) tile_load(NB - 2, 0);
   // x_{NB} = 0
-  for (int e = threadIdx.x; e < 64 * NT; e += NTHR) vb[1][(e / NT) * kMfVP + e % NT] = 0.0;
+  for (int e = threadIdx.x; e < 64 * NT; e += NTHR) vb[1][(e / NT) * kMfVP + e % NT] = AT(0);
   __syncthreads();
   double rz = 0.0, qz = 0.0;  // column li of this lane's rows
   auto bwd_body = [&](const int b, auto parc) {
     constexpr int par = decltype(parc)::v;  // b & 1
     const int j0 = 64 * b;
-    const double* T = tile;
-    double vv[4], rp[4], qp[4];
+    const AT* T = tile;
+    AT vv[4];
+    double rp[4], qp[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = j0 + drow(v);
       const bool ok = row < N;
-      vv[v] = ok ? out[vi(row, li)] : 0.0;
+      vv[v] = ok ? (AT)out[vi(row, li)] : AT(0);
       rp[v] = (ok && mode == 2) ? rin[vi(row, li)] : 0.0;
       qp[v] = (ok && mode == 2) ? qv[vi(row, li)] : 0.0;
     }
@@ -1061,20 +1086,20 @@ __global__ __launch_bounds__(256) void k_localt_mf(
     // before the passes: A[row 16 w + li][slot q0 + lk] of z += phat eta
     constexpr int NPA = 8;  // slots 0..31 fetched ahead, the rest when used
     const int ra = j0 + 16 * w + li;
-    double pa[NPA];
+    AT pa[NPA];
 #pragma unroll
     for (int c = 0; c < NPA; ++c) {
       const int q = 4 * c + lk;
-      pa[c] = (q < ns && ra < N) ? P[(size_t)q * N + ra] : 0.0;
+      pa[c] = (q < ns && ra < N) ? (AT)P[(size_t)q * N + ra] : AT(0);
     }
     // pass A: s = out_b - U^T x_{b+1}
-    am_mf_d4 acc;
+    V acc;
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[v] = vv[v];
     {
       const int ii = 16 * w + li;  // output row ii, tile row jj
       acc = mf_pass(
-          acc, [&](int kk) { const int jj = 4 * kk + lk; return jj <= ii ? -T[ii * PITCH + jj] : 0.0; },
+          acc, [&](int kk) { const int jj = 4 * kk + lk; return jj <= ii ? -T[ii * PITCH + jj] : AT(0); },
           [&](int kk) { return vb[1][(4 * kk + lk) * kMfVP + li]; });
     }
 #pragma unroll
@@ -1084,7 +1109,7 @@ __global__ __launch_bounds__(256) void k_localt_mf(
     {
       const int ii = 16 * w + li;
       acc = mf_pass(
-          acc, [&](int kk) { const int jj = 4 * kk + lk; return jj > ii ? T[ii * PITCH + jj] : 0.0; },
+          acc, [&](int kk) { const int jj = 4 * kk + lk; return jj > ii ? T[ii * PITCH + jj] : AT(0); },
           [&](int kk) { return vb[0][(4 * kk + lk) * kMfVP + li]; });
     }
 #pragma unroll
@@ -1094,22 +1119,23 @@ __global__ __launch_bounds__(256) void k_localt_mf(
     for (int c = 0; c < NPA; ++c) {
       if (4 * c >= ns) break;  // uniform
       const int q = 4 * c + lk;
-      const double e = q < ns ? eta_s[q * NT + li] : 0.0;
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[c], e, acc, 0, 0, 0);
+      const AT e = q < ns ? eta_s[q * NT + li] : AT(0);
+      acc = mf4(pa[c], e, acc);
     }
     for (int c = NPA; 4 * c < ns; ++c) {
       const int q = 4 * c + lk;
-      const double av = (q < ns && ra < N) ? P[(size_t)q * N + ra] : 0.0;
-      const double e = q < ns ? eta_s[q * NT + li] : 0.0;
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, e, acc, 0, 0, 0);
+      const AT av = (q < ns && ra < N) ? (AT)P[(size_t)q * N + ra] : AT(0);
+      const AT e = q < ns ? eta_s[q * NT + li] : AT(0);
+      acc = mf4(av, e, acc);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = j0 + drow(v);
       if (row < N) {
-        out[vi(row, li)] = acc[v];
-        rz = fma(rp[v], acc[v], rz);
-        qz = fma(qp[v], acc[v], qz);
+        const double zv = (double)acc[v];
+        out[vi(row, li)] = zv;
+        rz = fma(rp[v], zv, rz);
+        qz = fma(qp[v], zv, qz);
       }
     }
     __syncthreads();  // every wave is done with tile b
@@ -1322,12 +1348,12 @@ hipError_t localt_shape(DeviceState& d, const double* r, double* z, const double
     if (bk == 0) {
       using S = TileAt<FT, 1, NT, I>;
       bool mf = false;
-      if constexpr (NT == 16 && sizeof(FT) == 8) {
+      if constexpr (NT == 16) {
         if (!d.fuse_eta) {
           mf = true;
-          am_launch(d, bk == first_bk, bk == last_bk, k_localt_mf<16>, dim3(nb), dim3(256), st,
-                    d.d_bucket_sub[bk], d.sub_ptr, d.roff, d.fac_off, (const double*)d.Lc,
-                    (const double*)d.invd, r, z, mode, d.isub_ptr, d.isub_list, d.mbf_off, d.mbf,
+          am_launch(d, bk == first_bk, bk == last_bk, k_localt_mf<FT, 16>, dim3(nb), dim3(256), st,
+                    d.d_bucket_sub[bk], d.sub_ptr, d.roff, d.fac_off, (const FT*)d.Lc,
+                    (const IT*)d.invd, r, z, mode, d.isub_ptr, d.isub_list, d.mbf_off, d.mbf,
                     eta, d.q, d.red.pd, off, d.shared, d.n);
         }
       }

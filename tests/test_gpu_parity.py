@@ -352,6 +352,48 @@ def test_pcg_16_rhs_bisect(prec):
     h.close()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_matrix_core_16_rhs_reduced_precision(prec):
+    """16 right-hand sides with FP32 or BF16 factors on the FP32 matrix
+    cores (window-64 subdomains; the interface solve as its own launches, so
+    the local kernel is the matrix-core one).  The apply is a perturbed
+    AlgMortar: its distance from the oracle's FP64 apply must stay within
+    twice that of the vector-unit kernel with the same factors (the same
+    rounded factors and FP32 arithmetic, another summation order; the handle
+    with the interface solve fused into the local kernel uses it), and both
+    below 1e-2.  PCG (flexible, FP64 outer loop) at tol 1e-10: columns 0, 5
+    and 15 within 1e-8 of the oracle's solutions, true residual <= 1e-9,
+    iterations at most 1.5x + 5 the oracle's."""
+    A, part, m, b, ora = setup_case("bisect")
+    rng = np.random.default_rng(160)
+    n = A.n
+    R = rng.standard_normal((16, n))
+    Zo = np.stack([ora.apply(R[c]) for c in range(16)])
+    hm = am.AlgMortar(A, part, m, prec=prec, max_nrhs=16, separate_iface=True)
+    hv = am.AlgMortar(A, part, m, prec=prec, max_nrhs=16)
+    Zm = cpu(hm.apply(gpu(R)))
+    Zv = cpu(hv.apply(gpu(R)))
+    for c in range(16):
+        em, ev = rel(Zm[c], Zo[c]), rel(Zv[c], Zo[c])
+        assert em <= 2.0 * ev + 1e-12 and em <= 1e-2, (c, em, ev)
+    hv.close()
+    B = np.zeros((16, n))
+    wells = rng.choice(n, size=32, replace=False)
+    for c in range(16):
+        B[c, wells[2 * c]] += 1.0
+        B[c, wells[2 * c + 1]] -= 1.0
+    B[0] = b
+    X, infos, _ = hm.pcg(gpu(B), 1e-10)
+    X = cpu(X)
+    As = A.to_scipy()
+    for c in (0, 5, 15):
+        ref = pcg(lambda v: As @ v, B[c], ora.apply, 1e-10)
+        assert rel(X[c], ref.x) <= 1e-8
+        assert infos[c]["converged"] == 1 and infos[c]["true_rel_res"] <= 1e-9
+        assert infos[c]["iterations"] <= 1.5 * ref.iterations + 5
+    hm.close()
+
+
 @pytest.mark.parametrize("dense", [False, True])
 @pytest.mark.parametrize("name,max_nrhs", [("c1", 1), ("layered", 1), ("ragged3d", 2),
                                            ("bisect", 2), ("layered", 4), ("ragged3d", 16),
