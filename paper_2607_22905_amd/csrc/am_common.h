@@ -138,14 +138,38 @@ __device__ __forceinline__ bool publish_partial(const double (&v)[NR], double* p
   return last != 0;
 }
 
+// tot[k] += part[b * NR + k] over the rows b = first, first + step, ... < nb,
+// in that order.  U rows at a time have their loads issued together: the
+// row index is clamped into range and a row past the end adds exact zeros,
+// so no branch separates the loads (a loop with one guarded load per row
+// waits for each load before the next).
+template <int NR>
+__device__ __forceinline__ void fold_rows(const double* __restrict__ part, int nb, int first,
+                                          int step, double (&tot)[NR]) {
+  constexpr int U = NR >= 8 ? 2 : 16 / NR;
+  for (int b0 = first; b0 < nb; b0 += U * step) {
+    double v[U][NR];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int b = min(b0 + u * step, nb - 1);
+#pragma unroll
+      for (int k = 0; k < NR; ++k) v[u][k] = part[(size_t)b * NR + k];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool ok = b0 + u * step < nb;
+#pragma unroll
+      for (int k = 0; k < NR; ++k) tot[k] += ok ? v[u][k] : 0.0;
+    }
+  }
+}
+
 template <int NR>
 __device__ __forceinline__ void reduce_partials(double (&tot)[NR], const double* partial,
                                                 unsigned nblocks, double* lds) {
 #pragma unroll
   for (int k = 0; k < NR; ++k) tot[k] = 0.0;
-  for (unsigned b = threadIdx.x; b < nblocks; b += blockDim.x)
-#pragma unroll
-    for (int k = 0; k < NR; ++k) tot[k] += partial[(size_t)b * NR + k];
+  fold_rows<NR>(partial, (int)nblocks, threadIdx.x, blockDim.x, tot);
   block_sum<NR>(tot, lds);
 }
 
@@ -180,9 +204,7 @@ __device__ __forceinline__ bool stop_test(const double* __restrict__ pb, int npb
   double rr[NR];
 #pragma unroll
   for (int k = 0; k < NR; ++k) rr[k] = 0.0;
-  for (int b = lane; b < npb; b += 64)
-#pragma unroll
-    for (int k = 0; k < NR; ++k) rr[k] += pb[(size_t)b * NR + k];
+  fold_rows<NR>(pb, npb, lane, 64, rr);
 #pragma unroll
   for (int k = 0; k < NR; ++k) rr[k] = wave_sum(rr[k]);
   int alld = 1;

@@ -164,8 +164,13 @@ __global__ __launch_bounds__(256) void k_nd_top(
   nd_wave_each<NR>(acc, [&](int l, int k, double v) { out[(size_t)(64 * rb + l) * NR + k] = v; });
 }
 
-// eta_T = sum of the part sums in part order, to eta2 (ND order, for pass 1)
-// and to eta (original order).
+// eta_T = sum of the part sums, to eta2 (ND order, for pass 1) and to eta
+// (original order).  Eight neighbouring lanes share an output: lane u sums
+// the parts u, u + 8, ... in order (their loads all in flight), then the
+// eight lane sums are added pairwise by shuffles (every lane ends with the
+// same bits, as a + b = b + a exactly).  The order is fixed, so the result
+// is the same on every run.
+constexpr int kNdFoldLanes = 8;
 template <int NR>
 __global__ __launch_bounds__(256) void k_nd_fold(int R, int ldC, int P,
                                                  const double* __restrict__ ypart,
@@ -173,14 +178,21 @@ __global__ __launch_bounds__(256) void k_nd_fold(int R, int ldC, int P,
                                                  double* __restrict__ eta2, double* __restrict__ eta,
                                                  int pcg, int init, const PcgShared* sh) {
   if (pcg && !init && all_done(sh)) return;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)R * NR) return;
-  const int64_t r = t / NR;
-  const int k = (int)(t % NR);
+  const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kNdFoldLanes;
+  const int u = threadIdx.x % kNdFoldLanes;
+  const bool ok = t < (int64_t)R * NR;  // the lanes of an output agree
+  const int64_t tc = ok ? t : 0;
+  const int64_t r = tc / NR;
+  const int k = (int)(tc % NR);
   double v = 0.0;
-  for (int p = 0; p < P; ++p) v += ypart[((size_t)p * ldC + r) * NR + k];
-  eta2[r * NR + k] = v;
-  eta[(size_t)ord_top[r] * NR + k] = v;
+#pragma unroll 8
+  for (int p = u; p < P; p += kNdFoldLanes) v += ypart[((size_t)p * ldC + r) * NR + k];
+#pragma unroll
+  for (int off = 1; off < kNdFoldLanes; off <<= 1) v += __shfl_xor(v, off, 64);
+  if (ok && u == 0) {
+    eta2[r * NR + k] = v;
+    eta[(size_t)ord_top[r] * NR + k] = v;
+  }
 }
 
 // r_T = b_T - S_TB y_B, one thread per (top row, column), into eta2 (which
@@ -257,7 +269,8 @@ static void nd_solve_t(DeviceState& d, hipStream_t st, int pcg, int init) {
                   nd.per, nrb, nd.ord + nd.nrows, d.bpart, nd.t_ptr, nd.t_pos, nd.t_val, nd.y1,
                   nd.eta2, nd.ypart, pcg, init, d.shared);
   }
-  const unsigned nb = (unsigned)std::max<int64_t>(1, ((int64_t)nd.R * NR + 255) / 256);
+  const unsigned nb =
+      (unsigned)std::max<int64_t>(1, ((int64_t)nd.R * NR * kNdFoldLanes + 255) / 256);
   if (nd.R > 0)
     am_launch(d, false, false, k_nd_fold<NR>, dim3(nb), dim3(256), st, nd.R, nd.ldC, nd.P,
               nd.ypart, nd.ord + nd.nrows, nd.eta2, d.eta, pcg, init, d.shared);

@@ -109,12 +109,8 @@ __global__ __launch_bounds__(256) void k_spmv_p(int64_t n, int w, const int32_t*
   double rzq[2 * KG];
 #pragma unroll
   for (int k = 0; k < 2 * KG; ++k) rzq[k] = 0.0;
-  for (int bb = threadIdx.x; bb < npd; bb += blockDim.x)
-#pragma unroll
-    for (int k = 0; k < KG; ++k) {
-      rzq[k] += pd[(size_t)bb * 2 * NT + k0 + k];
-      rzq[KG + k] += pd[(size_t)bb * 2 * NT + NT + k0 + k];
-    }
+  static_assert(TR == 1, "one group of columns");
+  fold_rows<2 * NT>(pd, npd, threadIdx.x, blockDim.x, rzq);  // rows of pd: (r, z) then (q, z)
   double pq[KG];
 #pragma unroll
   for (int k = 0; k < KG; ++k) pq[k] = 0.0;
@@ -340,10 +336,8 @@ __global__ __launch_bounds__(256) void k_update_xr(
   double pqs[KG];
 #pragma unroll
   for (int k = 0; k < KG; ++k) pqs[k] = 0.0;
-  if (!init)
-    for (int bb = threadIdx.x; bb < npa; bb += blockDim.x)
-#pragma unroll
-      for (int k = 0; k < KG; ++k) pqs[k] += pa[(size_t)bb * NT + k0 + k];
+  static_assert(TR == 1, "one group of columns");
+  if (!init) fold_rows<NT>(pa, npa, threadIdx.x, blockDim.x, pqs);
   const int64_t base = sub_ptr[s];
   const int N = (int)(sub_ptr[s + 1] - base);
   const int64_t i0 = isub_ptr[s];
@@ -539,10 +533,20 @@ __global__ __launch_bounds__(1024) void k_pcg_coef(int kind, const double* __res
   const int c = blockIdx.x;
   const int stride = kind == 0 ? 2 * NT : NT;
   double v[2] = {0.0, 0.0};
-#pragma unroll 4
-  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-    v[0] += part[(size_t)b * stride + c];
-    if (kind == 0) v[1] += part[(size_t)b * stride + NT + c];
+  for (int b0 = threadIdx.x; b0 < nb; b0 += 4 * blockDim.x) {  // four rows' loads together
+    double a[4][2];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int b = min(b0 + u * (int)blockDim.x, nb - 1);
+      a[u][0] = part[(size_t)b * stride + c];
+      a[u][1] = kind == 0 ? part[(size_t)b * stride + NT + c] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (b0 + u * (int)blockDim.x < nb) {
+        v[0] += a[u][0];
+        v[1] += a[u][1];
+      }
   }
   block_sum<2>(v, lds);
   if (threadIdx.x != 0) return;
