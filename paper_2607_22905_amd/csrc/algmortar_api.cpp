@@ -778,7 +778,8 @@ static am_status setup_impl(const am_csr* A, const int32_t* part, int32_t nparts
   d.red.max_blocks = (int)std::max<int64_t>((n + 255) / 256, st.m) + 1;
   d.red.spmv_blocks = (int)std::min<int64_t>((n + 255) / 256, 1024);
   SCHK(dalloc(al, &d.red.partial, (size_t)d.red.max_blocks * 2 * kMaxNRHS));
-  SCHK(dalloc(al, &d.red.pa, (size_t)d.red.spmv_blocks * kMaxNRHS));
+  // (p, Ap) partials: per SpMV workgroup (1-4 columns) or per subdomain (8-16)
+  SCHK(dalloc(al, &d.red.pa, (size_t)std::max<int64_t>(d.red.spmv_blocks, st.m) * kMaxNRHS));
   SCHK(dalloc(al, &d.red.pb, (size_t)st.m * kMaxNRHS));
   SCHK(dalloc(al, &d.red.pd, (size_t)st.m * 2 * kMaxNRHS));
   SCHK(dalloc(al, &d.red.coef, 2 * kMaxNRHS));

@@ -48,7 +48,7 @@ struct PcgShared {
 // atomics), and workgroup 0 stores the scalars for later launches; with 8-16
 // columns a one-workgroup-per-column launch folds them once into coef.
 struct Reduce {
-  double* pa = nullptr;         // (p, Ap) per SpMV block          [spmv_blocks][NR]
+  double* pa = nullptr;         // (p, Ap) per SpMV block (1-4 columns) or subdomain (8-16)
   double* pb = nullptr;         // ||r||^2 per subdomain            [m][NR]
   double* pd = nullptr;         // (r, z), (q, z) per subdomain     [m][2 NR]
   double* coef = nullptr;       // beta, alpha of 8-16 columns      [2][kMaxNRHS]

@@ -89,7 +89,7 @@ __global__ __launch_bounds__(256) void k_spmv_p(int64_t n, int w, const int32_t*
                                                 const double* __restrict__ pd, int npd,
                                                 double* __restrict__ pa, PcgScalars* sc,
                                                 PcgShared* sh, int parity) {
-  static_assert(NT <= 4, "8 and 16 columns: k_spmv_rows");
+  static_assert(NT <= 4, "8 and 16 columns: k_spmv_sub");
   constexpr int KG = KGroup<NT>::v, TR = NT / KG;
   __shared__ double lds[8 * KG];
   const int blk = blockIdx.x / TR, g = blockIdx.x % TR, k0 = g * KG;
@@ -585,66 +585,143 @@ __global__ __launch_bounds__(1024) void k_pcg_coef(int kind, const double* __res
   coef[(kind == 0 ? 0 : kMaxNRHS) + c] = cf;
 }
 
-// p_new = z + beta p_old, q = A p_new, (p, q) partials (as k_spmv_p), beta
-// from k_pcg_coef.
+// p_new = z + beta p_old, q = A p_new and the (p, q) partials for NT (8 or
+// 16) columns, one workgroup per subdomain, beta from k_pcg_coef.  The gathers
+// of A p_new dominate this product's traffic through the vector memory
+// path (seven neighbours, two vectors each, with p_new formed on the fly), so
+// the workgroup first forms p_new on its own rows and keeps the first
+// SubCap<NT> of them in LDS; a neighbour inside that range is then read from
+// LDS, any other one (another subdomain, or beyond the cap) from z and p_old
+// as before.  The NT / 4 lanes of a row are neighbours, each with four
+// columns.  The ELL rows of the product are loaded one pass ahead: the first
+// pass's before p_new is formed, the next pass's while the current one is
+// multiplied.
+template <int NT> struct SubCap { static constexpr int v = 8192 / NT; };  // 64 KB of p_new
 template <int NT, int MAXW>
-__global__ __launch_bounds__(256) void k_spmv_rows(int64_t n, int w, const int32_t* __restrict__ ec,
-                                                   const double* __restrict__ ev,
-                                                   const double* __restrict__ z,
-                                                   const double* __restrict__ pold,
-                                                   double* __restrict__ pnew,
-                                                   double* __restrict__ q,
-                                                   const double* __restrict__ coef,
-                                                   double* __restrict__ pa, PcgShared* sh) {
-  constexpr int KG = 4, TR = NT / KG, RW = 256 / TR;  // rows per workgroup step
-  __shared__ double lds[4 * NT];
-  const int g = threadIdx.x % TR, k0 = g * KG, rsub = threadIdx.x / TR;
+__global__ __launch_bounds__(512) void k_spmv_sub(
+    int64_t n, int w, const int32_t* __restrict__ ec, const double* __restrict__ ev,
+    const double* __restrict__ z, const double* __restrict__ pold, double* __restrict__ pnew,
+    double* __restrict__ q, const int64_t* __restrict__ sub_ptr, const double* __restrict__ coef,
+    double* __restrict__ pa, PcgShared* sh) {
+  static_assert(NT == 8 || NT == 16, "k_spmv_sub: 8 or 16 columns");
+  constexpr int KG = 4, TR = NT / KG, NTHR = 512, RW = NTHR / TR;
+  constexpr int CAP = SubCap<NT>::v;
+  constexpr int RPA = CAP / RW;  // rows per thread forming p_new: the LDS rows in one pass
+  __shared__ double ps[CAP * NT];
+  __shared__ double lds[8 * NT];
   if (*(volatile const int32_t*)&sh->all_done) return;  // uniform
-  // rows in grid-stride steps: at any time the whole grid works on one
-  // window of rows, so the gathered neighbours are mostly in cache (one
-  // contiguous chunk per workgroup, contiguous per XCD, measured slower:
-  // 1024 separate streams through the vectors and the ELL columns)
-  const int64_t step = (int64_t)gridDim.x * RW;
-  int64_t i = (int64_t)blockIdx.x * RW + rsub;
+  const int s = blockIdx.x;
+  const int g = threadIdx.x % TR, k0 = g * KG, rsub = threadIdx.x / TR;
+  const int64_t base = sub_ptr[s];
+  const int N = (int)(sub_ptr[s + 1] - base);
+  const int NL = min(N, CAP);  // rows held in LDS
   double beta[KG];
 #pragma unroll
   for (int k = 0; k < KG; ++k) beta[k] = coef[k0 + k];
-  double pq[KG];
-#pragma unroll
-  for (int k = 0; k < KG; ++k) pq[k] = 0.0;
-  for (; i < n; i += step) {
-    int32_t col[MAXW];
-    double v[MAXW];
+  // ELL row of the product (row index clamped into the subdomain)
+  int32_t col[MAXW];
+  double v[MAXW];
+  auto load_ell = [&](int r) {
+    const int64_t i = base + min(r, N - 1);
 #pragma unroll
     for (int c = 0; c < MAXW; ++c) {
       col[c] = c < w ? ec[(int64_t)c * n + i] : 0;
       v[c] = c < w ? ev[(int64_t)c * n + i] : 0.0;
     }
-    double zi[KG], pi[KG];
+  };
+  load_ell(rsub);
+  // p_new on the subdomain's rows
+  const double* zs = z + (size_t)base * NT + k0;
+  const double* ps_old = pold + (size_t)base * NT + k0;
+  for (int r0 = rsub; r0 < N; r0 += RPA * RW) {
+    double zi[RPA][KG], pi[RPA][KG];
 #pragma unroll
-    for (int k = 0; k < KG; ++k) {
-      zi[k] = z[(size_t)i * NT + k0 + k];
-      pi[k] = pold[(size_t)i * NT + k0 + k];
+    for (int u = 0; u < RPA; ++u) {
+      const int r = min(r0 + u * RW, N - 1);
+#pragma unroll
+      for (int k = 0; k < KG; ++k) {
+        zi[u][k] = zs[(size_t)r * NT + k];
+        pi[u][k] = ps_old[(size_t)r * NT + k];
+      }
     }
+#pragma unroll
+    for (int u = 0; u < RPA; ++u) {
+      const int r = r0 + u * RW;
+      if (r >= N) continue;
+#pragma unroll
+      for (int k = 0; k < KG; ++k) {
+        const double pn = fma(beta[k], pi[u][k], zi[u][k]);
+        pnew[(size_t)(base + r) * NT + k0 + k] = pn;
+        if (r < NL) ps[r * NT + k0 + k] = pn;
+      }
+    }
+  }
+  __syncthreads();
+  // q = A p_new on the subdomain's rows
+  double pq[KG];
+#pragma unroll
+  for (int k = 0; k < KG; ++k) pq[k] = 0.0;
+  for (int r = rsub; r < N; r += RW) {
+    int32_t cc[MAXW];
+    double vv[MAXW];
+#pragma unroll
+    for (int c = 0; c < MAXW; ++c) {
+      cc[c] = col[c];
+      vv[c] = v[c];
+    }
+    if (r + RW < N) load_ell(r + RW);  // the next pass's row, in flight meanwhile
     double acc[KG];
 #pragma unroll
     for (int k = 0; k < KG; ++k) acc[k] = 0.0;
 #pragma unroll
     for (int c = 0; c < MAXW; ++c) {
       if (c >= w) break;
-      const size_t o = (size_t)col[c] * NT + k0;
+      const int64_t j = (int64_t)cc[c] - base;
+      double pv[KG];
+      if (j >= 0 && j < NL) {
 #pragma unroll
-      for (int k = 0; k < KG; ++k) acc[k] = fma(v[c], fma(beta[k], pold[o + k], z[o + k]), acc[k]);
+        for (int k = 0; k < KG; ++k) pv[k] = ps[(int)j * NT + k0 + k];
+      } else {
+        const size_t o = (size_t)cc[c] * NT + k0;
+#pragma unroll
+        for (int k = 0; k < KG; ++k) pv[k] = fma(beta[k], pold[o + k], z[o + k]);
+      }
+#pragma unroll
+      for (int k = 0; k < KG; ++k) acc[k] = fma(vv[c], pv[k], acc[k]);
+    }
+    double pn[KG];
+    if (r < NL) {
+#pragma unroll
+      for (int k = 0; k < KG; ++k) pn[k] = ps[r * NT + k0 + k];
+    } else {
+      const size_t o = (size_t)(base + r) * NT + k0;
+#pragma unroll
+      for (int k = 0; k < KG; ++k) pn[k] = fma(beta[k], pold[o + k], z[o + k]);
     }
 #pragma unroll
     for (int k = 0; k < KG; ++k) {
-      const double pn = fma(beta[k], pi[k], zi[k]);
-      pnew[(size_t)i * NT + k0 + k] = pn;
-      q[(size_t)i * NT + k0 + k] = acc[k];
-      pq[k] = fma(pn, acc[k], pq[k]);
+      q[(size_t)(base + r) * NT + k0 + k] = acc[k];
+      pq[k] = fma(pn[k], acc[k], pq[k]);
     }
   }
-  group_sum<NT>(pq, lds, pa + (size_t)blockIdx.x * NT);
+  // (p, q) partial of this subdomain: lanes of a group, then the waves in order
+  {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < KG; ++k)
+#pragma unroll
+      for (int off = TR; off < 64; off <<= 1) pq[k] += __shfl_xor(pq[k], off, 64);
+    if (lane < TR)
+#pragma unroll
+      for (int k = 0; k < KG; ++k) lds[wv * NT + lane * KG + k] = pq[k];
+    __syncthreads();
+    if (threadIdx.x < NT) {
+      double t = 0.0;
+#pragma unroll
+      for (int u = 0; u < NTHR / 64; ++u) t += lds[u * NT + threadIdx.x];
+      pa[(size_t)s * NT + threadIdx.x] = t;
+    }
+  }
 }
 
 // x += alpha p, r -= alpha q, ||r||^2 partials and the interface partial
@@ -866,10 +943,11 @@ hipError_t launch_pcg_init(DeviceState& d, int nr, double tol, int maxit, int fl
   return hipGetLastError();
 }
 
-// SpMV workgroups (and so (p, Ap) partials per column): at most 1024, one
-// round of resident workgroups.  With up to four columns every workgroup of
-// the SpMV and update launches folds the partials it needs itself; with 8-16
-// columns k_pcg_coef folds them once per launch.
+// SpMV workgroups with up to four columns (and so (p, Ap) partials per
+// column): at most 1024, one round of resident workgroups.  Every workgroup
+// of the SpMV and update launches folds the partials it needs itself.  (With
+// 8-16 columns the SpMV has one workgroup per subdomain and k_pcg_coef folds
+// the partials once per launch.)
 template <int NR>
 static int spmv_grid(const DeviceState& d) {
   return std::max(1, d.red.spmv_blocks);
@@ -878,9 +956,9 @@ static int spmv_grid(const DeviceState& d) {
 static hipError_t update_xr(DeviceState& d, int nr, int parity, int init, hipStream_t s) {
   const double* pn = d.p[1 - parity];
   AM_NR_SWITCH(nr, if constexpr (NR >= 8) {
-    if (!init)
-      am_launch(d, true, false, k_pcg_coef<NR>, dim3(NR), dim3(1024), s, 1, d.red.pa,
-                spmv_grid<NR>(d), d.red.coef, d.sc, d.shared, parity);
+    if (!init)  // (p, Ap) partials: one per subdomain (k_spmv_sub)
+      am_launch(d, true, false, k_pcg_coef<NR>, dim3(NR), dim3(1024), s, 1, d.red.pa, d.m,
+                d.red.coef, d.sc, d.shared, parity);
     auto kern = (init ? &k_update_rows<NR, true> : &k_update_rows<NR, false>);
     am_launch(d, init != 0, true, kern, dim3(d.m), dim3(256), s, d.n, d.sub_ptr, d.isub_ptr,
               d.mbf_off, d.mbf, d.bdst, pn, d.q, d.x, d.r, d.bpart, d.red.coef, d.red.pb,
@@ -915,8 +993,8 @@ hipError_t launch_pcg_spmv(DeviceState& d, int nr, int parity, hipStream_t s) {
     AM_NR_SWITCH(nr, if constexpr (NR >= 8) {
       am_launch(d, true, false, k_pcg_coef<NR>, dim3(NR), dim3(1024), s, 0, d.red.pd, d.m,
                 d.red.coef, d.sc, d.shared, parity);
-      am_launch(d, false, true, k_spmv_rows<NR, MW>, dim3(spmv_grid<NR>(d)), dim3(256), s, d.n,
-                d.ell_w, d.ell_col, d.ell_val, d.z, po, pn, d.q, d.red.coef, d.red.pa, d.shared);
+      am_launch(d, false, true, k_spmv_sub<NR, MW>, dim3(d.m), dim3(512), s, d.n, d.ell_w,
+                d.ell_col, d.ell_val, d.z, po, pn, d.q, d.sub_ptr, d.red.coef, d.red.pa, d.shared);
     } else {
       am_launch(d, true, true, k_spmv_p<NR, MW>, dim3(spmv_grid<NR>(d)), dim3(256), s, d.n,
                 d.ell_w, d.ell_col, d.ell_val, d.z, po, pn, d.q, d.red.pd, d.m, d.red.pa, d.sc,
