@@ -290,7 +290,7 @@ def main():
                     help="contrast sweep K -> K^theta (c2, c6)")
     ap.add_argument("--smooth-steps", type=int, default=0,
                     help="block-Jacobi steps before and after the AlgMortar correction (Sec. 5.4)")
-    ap.add_argument("--smooth-blocks", default="8,8,32",
+    ap.add_argument("--smooth-blocks", default="8,8,16",
                     help="block sizes bx,by,bz of the smoothing partition (Cartesian workloads)")
     ap.add_argument("--grad", type=int, default=0, metavar="K",
                     help="also time K gradient evaluations of a least-squares loss on observed "

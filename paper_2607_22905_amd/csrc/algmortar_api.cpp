@@ -233,23 +233,23 @@ am_status algmortar_destroy(am_handle h) {
     delete h;
     return AM_OK;
   }
-  hipSetDevice(h->d.device);
-  for (void* p : h->sm_allocs) hipFree(p);
+  (void)hipSetDevice(h->d.device);
+  for (void* p : h->sm_allocs) (void)hipFree(p);
   if (h->bj) algmortar_destroy(h->bj);
-  if (h->d.graph) hipGraphExecDestroy(h->d.graph);
+  if (h->d.graph) (void)hipGraphExecDestroy(h->d.graph);
   for (hipGraphExec_t g : h->d.graph_short)
-    if (g) hipGraphExecDestroy(g);
-  for (void* p : h->d.allocs) hipFree(p);
-  for (void* p : h->vm.allocs) hipFree(p);
-  if (h->d.h_flags) hipHostFree(h->d.h_flags);
-  if (h->d.h_sc) hipHostFree(h->d.h_sc);
-  if (h->ev0) hipEventDestroy(h->ev0);
-  if (h->ev1) hipEventDestroy(h->ev1);
+    if (g) (void)hipGraphExecDestroy(g);
+  for (void* p : h->d.allocs) (void)hipFree(p);
+  for (void* p : h->vm.allocs) (void)hipFree(p);
+  if (h->d.h_flags) (void)hipHostFree(h->d.h_flags);
+  if (h->d.h_sc) (void)hipHostFree(h->d.h_sc);
+  if (h->ev0) (void)hipEventDestroy(h->ev0);
+  if (h->ev1) (void)hipEventDestroy(h->ev1);
   for (hipEvent_t e : h->evp)
-    if (e) hipEventDestroy(e);
+    if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : h->evf)
-    if (e) hipEventDestroy(e);
-  if (h->own) hipStreamDestroy(h->own);
+    if (e) (void)hipEventDestroy(e);
+  if (h->own) (void)hipStreamDestroy(h->own);
   delete h;
   return AM_OK;
 }
@@ -422,10 +422,10 @@ static hipError_t interface_inverse(DeviceState& d, hipStream_t st) {
                    : dense_cholesky_inverse(d, L, Li, part, st);
   const hipError_t he2 = hipStreamSynchronize(st);
   if (he == hipSuccess) he = he2;
-  hipFree(L);
-  hipFree(Li);
-  hipFree(part);
-  hipFree(Sp);
+  (void)hipFree(L);
+  (void)hipFree(Li);
+  (void)hipFree(part);
+  (void)hipFree(Sp);
   return he;
 }
 
@@ -823,7 +823,7 @@ static am_status setup_impl(const am_csr* A, const int32_t* part, int32_t nparts
   // set-up solves of the basis functions only
   for (auto it = d.allocs.begin(); it != d.allocs.end(); ++it)
     if (*it == d.Lr) {
-      hipFree(*it);
+      (void)hipFree(*it);
       d.allocs.erase(it);
       break;
     }
@@ -945,7 +945,7 @@ am_status algmortar_tile_choice(am_handle h, int32_t nrhs, int32_t* choice, int3
 }
 
 static void drop_smoother(am_handle h) {
-  for (void* p : h->sm_allocs) hipFree(p);
+  for (void* p : h->sm_allocs) (void)hipFree(p);
   h->sm_allocs.clear();
   if (h->bj) algmortar_destroy(h->bj);
   h->bj = nullptr;
@@ -1120,7 +1120,7 @@ am_status algmortar_update_values(am_handle h, const am_csr* A, void* stream) {
   if (he == hipSuccess && d.NL > 0) he = interface_inverse(d, st);
   const hipError_t he3 = hipStreamSynchronize(st);
   if (he == hipSuccess) he = he3;
-  hipFree(Lr);
+  (void)hipFree(Lr);
   d.Lr = nullptr;
   HCHK(he);
   int32_t fl[4];
@@ -1156,6 +1156,7 @@ am_status algmortar_set_smoother(am_handle h, const int32_t* blocks, int32_t nbl
   HCHK(hipDeviceSynchronize());
   (void)stream;
   drop_smoother(h);
+  d.graph_nrhs = 0;  // the captured chunks hold the old launch sequence
   if (steps == 0) return AM_OK;
   if (!blocks) return fail(h, AM_ERR_ARG, "null block partition");
   std::string e;
@@ -1392,9 +1393,28 @@ am_status algmortar_local_solve(am_handle h, const double* r, double* pbar, void
 
 static constexpr int kChunk = 8;  // iterations per captured graph (even: p ping-pong)
 
-static hipError_t run_chunk(DeviceState& d, int nr, hipStream_t st, int len = kChunk) {
+// One PCG iteration of the smoothed preconditioner: the smoothed apply (some
+// 4 nu + 10 launches), the (r, z), (q, z) partials, the SpMV, the update and
+// the stop test.  After the stop, the apply and the partials still run (on
+// the stopped r, into z and the partials, which nothing reads any more);
+// the SpMV, update and stop test return at once.
+static hipError_t smoothed_iteration(DeviceState& d, SmoothDevice& sm, int nr, int parity,
+                                     hipStream_t st) {
+  hipError_t e = launch_smoothed_apply(d, sm, d.r, d.z, nr, st);
+  if (e == hipSuccess) e = launch_smooth_dots(d, nr, st);
+  if (e == hipSuccess) e = launch_pcg_spmv(d, nr, parity, st);
+  if (e == hipSuccess) e = launch_pcg_update(d, nr, parity, st);
+  if (e == hipSuccess) e = launch_stop_test(d, nr, 0, st);
+  return e;
+}
+
+// len iterations (even: the p ping-pong keeps its parity), smoothed when sm
+// is given
+static hipError_t run_chunk(DeviceState& d, int nr, hipStream_t st, int len = kChunk,
+                            SmoothDevice* sm = nullptr) {
   for (int it = 0; it < len; ++it) {
-    hipError_t e = launch_pcg_iteration(d, nr, it & 1, st);
+    hipError_t e = sm ? smoothed_iteration(d, *sm, nr, it & 1, st)
+                      : launch_pcg_iteration(d, nr, it & 1, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -1518,29 +1538,17 @@ static am_status pcg_impl(am_handle h, const double* b, double* x, int32_t nrhs,
   // operator: reduced-precision factors, an interface solve stopped by a
   // tolerance
   HCHK(launch_pcg_init(d, nr, tol, maxit, (d.prec != AM_FP64 || d.ix.on) ? 1 : 0, st));
+  // The smoothed preconditioner runs the same chunks of iterations, its
+  // iteration being smoothed_iteration; its first residual norm and stop
+  // test come from the update launch in its initial form.
+  SmoothDevice* smp = smooth ? &h->sm : nullptr;
   if (smooth) {
-    // Smoothed preconditioner (some 4 nu + 10 launches per apply): plain
-    // launches, and the stop flag is read after each stop test so that no
-    // apply runs after convergence.
-    auto stopped = [&](int init) -> hipError_t {
-      hipError_t e = launch_stop_test(d, nr, init, st);
-      if (e != hipSuccess) return e;
-      if ((e = hipMemcpyAsync(d.h_flags, &d.shared->all_done, sizeof(int32_t),
-                              hipMemcpyDeviceToHost, st)) != hipSuccess)
-        return e;
-      return hipStreamSynchronize(st);
-    };
     HCHK(launch_pcg_rr0(d, nr, st));
-    HCHK(stopped(1));
-    for (int it = 0; !d.h_flags[0] && it <= maxit + 1; ++it) {
-      HCHK(launch_smoothed_apply(d, h->sm, d.r, d.z, nr, st));
-      HCHK(launch_smooth_dots(d, nr, st));
-      HCHK(launch_pcg_spmv(d, nr, it & 1, st));
-      HCHK(launch_pcg_update(d, nr, it & 1, st));
-      HCHK(stopped(0));
-    }
+    HCHK(launch_stop_test(d, nr, 1, st));
   } else {
-  HCHK(launch_pcg_start(d, nr, st));
+    HCHK(launch_pcg_start(d, nr, st));
+  }
+  {
   const bool use_graph = !(h->opt.flags & AM_FLAG_NO_GRAPH) && !prof;
   if (use_graph && (d.graph == nullptr || d.graph_nrhs != nr)) {
     // chunks of 8 iterations, and of 2, 4 and 6 for the end of a solve
@@ -1556,12 +1564,12 @@ static am_status pcg_impl(am_handle h, const double* b, double* x, int32_t nrhs,
     for (int i = 0; i < 4; ++i) {
       hipGraph_t g = nullptr;
       HCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-      hipError_t ce = run_chunk(d, nr, st, lens[i]);
+      hipError_t ce = run_chunk(d, nr, st, lens[i], smp);
       hipError_t ee = hipStreamEndCapture(st, &g);
       if (ce != hipSuccess) return fail(h, AM_ERR_HIP, std::string("capture: ") + hipGetErrorString(ce));
       if (ee != hipSuccess) return fail(h, AM_ERR_HIP, std::string("end capture: ") + hipGetErrorString(ee));
       hipError_t ie = hipGraphInstantiate(slots[i], g, nullptr, nullptr, 0);
-      hipGraphDestroy(g);
+      (void)hipGraphDestroy(g);
       if (ie != hipSuccess) {
         *slots[i] = nullptr;
         return fail(h, AM_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(ie));
@@ -1651,7 +1659,7 @@ static am_status pcg_impl(am_handle h, const double* b, double* x, int32_t nrhs,
       if (use_graph)
         HCHK(hipGraphLaunch(len == kChunk ? d.graph : d.graph_short[len / 2 - 1], st));
       else
-        HCHK(run_chunk(d, nr, st, len));
+        HCHK(run_chunk(d, nr, st, len, smp));
       const int slot = c_launch & 1;
       HCHK(hipMemcpyAsync(d.h_sc + (size_t)slot * kMaxNRHS, d.sc, sizeof(PcgScalars) * nr,
                           hipMemcpyDeviceToHost, st));
@@ -1981,8 +1989,8 @@ am_status am_tpfa_face_grad(am_tpfa t, const double* logK, const double* p, cons
 
 am_status am_tpfa_destroy(am_tpfa t) {
   if (!t) return AM_OK;
-  hipSetDevice(t->t.device);
-  for (void* p : t->t.allocs) hipFree(p);
+  (void)hipSetDevice(t->t.device);
+  for (void* p : t->t.allocs) (void)hipFree(p);
   delete t;
   return AM_OK;
 }
