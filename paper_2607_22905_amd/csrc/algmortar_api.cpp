@@ -250,6 +250,9 @@ am_status algmortar_destroy(am_handle h) {
   for (hipEvent_t e : h->evf)
     if (e) (void)hipEventDestroy(e);
   if (h->own) (void)hipStreamDestroy(h->own);
+  if (h->d.side) (void)hipStreamDestroy(h->d.side);
+  if (h->d.ev_fork) (void)hipEventDestroy(h->d.ev_fork);
+  if (h->d.ev_join) (void)hipEventDestroy(h->d.ev_join);
   delete h;
   return AM_OK;
 }
@@ -563,6 +566,9 @@ static am_status setup_impl(const am_csr* A, const int32_t* part, int32_t nparts
   // which looks it up again, and does not affect the rest of the library)
   (void)static_scratch_init(d.device);
   SCHK(hipStreamCreateWithFlags(&h->own, hipStreamNonBlocking));
+  SCHK(hipStreamCreateWithFlags(&d.side, hipStreamNonBlocking));
+  SCHK(hipEventCreateWithFlags(&d.ev_fork, hipEventDisableTiming));
+  SCHK(hipEventCreateWithFlags(&d.ev_join, hipEventDisableTiming));
   SCHK(hipEventCreate(&h->ev0));
   SCHK(hipEventCreate(&h->ev1));
   SCHK(hipEventCreateWithFlags(&h->evf[0], hipEventDisableTiming));

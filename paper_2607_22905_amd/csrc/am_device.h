@@ -143,6 +143,10 @@ struct DeviceState {
   // operation carry (am_launch), and whether they were attached
   hipEvent_t prof_ev[2] = {nullptr, nullptr};
   bool prof_used[2] = {false, false};
+  // second stream (default priority) and the events of the fork and join
+  // that run the two window buckets of the local kernel side by side
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
   // device ordering and permuted matrix
   int32_t* dperm = nullptr;    // [n] device position -> original index

@@ -1173,6 +1173,250 @@ __global__ __launch_bounds__(256) void k_localt_mf(
   }
 }
 
+// The same for window 128 (a bandwidth of 65-128 rows): a column keeps its
+// 128 band entries in a ring of two 64-row chunks, so that in tile b the
+// chunk b & 1 holds the rows of block b (strictly lower part: the inverted
+// diagonal block; upper part with the diagonal: the coupling L_{b+2,b} to
+// block b + 2) and the other chunk the full coupling L_{b+1,b}.
+//   forward  y_b = t_b + Nlow_b t_b,   out_b = dinv y_b,
+//            t_{b+1} = u_{b+1} - L_{b+1,b} y_b,   u_{b+2} = r_{b+2} - L_{b+2,b} y_b
+//   backward s_b = out_b - L_{b+1,b}^T x_{b+1} - L_{b+2,b}^T x_{b+2},
+//            x_b = s_b + Nlow_b^T s_b,  z_b = x_b + sum_q phat_q eta_q, dots
+// Three block vectors live in LDS (forward: t, y, u; backward: x_{b+1},
+// x_{b+2}, s, with x_b written over x_{b+2}), with one tile buffer of two
+// chunks: about 100 KB, so that a workgroup of the window-64 kernel still
+// fits beside it on a CU (the two buckets run side by side).
+template <typename FT, int NT>
+__global__ __launch_bounds__(256) void k_localt_mf2(
+    const int32_t* __restrict__ subs, const int64_t* __restrict__ sub_ptr,
+    const int64_t* __restrict__ roff, const int64_t* __restrict__ fac_off,
+    const FT* __restrict__ Lc, const typename AccT<FT>::T* __restrict__ dinv, const double* rin,
+    double* out, int mode, const int64_t* __restrict__ isub_ptr,
+    const int32_t* __restrict__ isub_list, const int64_t* __restrict__ mbf_off,
+    const double* __restrict__ mbf, const double* __restrict__ eta, const double* __restrict__ qv,
+    double* __restrict__ partial, unsigned blk_off, PcgShared* sh, int64_t nrows) {
+  static_assert(NT == 16, "one 16-column matrix-core tile");
+  using AT = typename AccT<FT>::T;
+  using V = typename MfAcc<AT>::V;
+  constexpr int PITCH = 65;
+  constexpr int CH = 64 * PITCH;
+  constexpr int NTHR = 256;
+  constexpr int WP = 128;
+  constexpr int VEC = 16 / (int)sizeof(FT);
+  constexpr int NLD = 64 * WP / (VEC * NTHR);
+  __shared__ AT tile[2 * CH];
+  __shared__ AT vb[3][64 * kMfVP];
+  __shared__ AT eta_s[64 * NT];
+  __shared__ double dots[4][2 * NT];
+
+  const int s = subs[blockIdx.x];
+  const int64_t base = sub_ptr[s];
+  const int N = (int)(sub_ptr[s + 1] - base);
+  const int64_t ro = roff[s];
+  const int NP = (int)(roff[s + 1] - ro);
+  const int NB = NP / 64;
+  const FT* lc = Lc + fac_off[s];
+  const AT* dv = dinv + ro;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int li = lane % 16, lk = lane / 16;
+  const int64_t i0 = isub_ptr[s];
+  const int ns = mode >= 1 ? (int)(isub_ptr[s + 1] - i0) : 0;
+  const double* P = mbf + mbf_off[s];
+  auto vi = [&](int row, int k) { return vix<NT>(nrows, base + row, k); };
+
+  uint4 pre[NLD];
+  auto tile_load = [&](int b) {
+    const uint4* src = reinterpret_cast<const uint4*>(lc + (size_t)64 * b * WP);
+#pragma unroll
+    for (int u = 0; u < NLD; ++u) pre[u] = src[u * NTHR + threadIdx.x];
+  };
+  auto tile_store = [&]() {
+#pragma unroll
+    for (int u = 0; u < NLD; ++u) {
+      const int e0 = (u * NTHR + (int)threadIdx.x) * VEC;  // column e0 / WP, slots e0 % WP ..
+      const int col = e0 / WP, slot = e0 % WP;
+      AT* dst = tile + (slot / 64) * CH + col * PITCH + (slot % 64);
+      FT v[VEC];
+      __builtin_memcpy(v, &pre[u], 16);
+#pragma unroll
+      for (int t = 0; t < VEC; ++t) dst[t] = (AT)widen_lds(v[t]);
+    }
+  };
+  auto drow = [&](int v) { return 16 * w + MfAcc<AT>::row(lk, v); };
+  auto ldr = [&](int row) -> AT { return (row >= 0 && row < N) ? (AT)rin[vi(row, li)] : AT(0); };
+
+  tile_load(0);
+  if (mode == 2 && all_done(sh)) return;
+  for (int t = threadIdx.x; t < ns * NT; t += NTHR)
+    eta_s[t] = (AT)eta[(size_t)isub_list[i0 + t / NT] * NT + (t % NT)];
+  tile_store();
+  if (1 < NB) tile_load(1);
+  // t_0 = r of block 0 (vb[0]); u_1 = r of block 1 (vb[2])
+  for (int e = threadIdx.x; e < 64 * NT; e += NTHR) {
+    const int row = e / NT, k = e % NT;
+    vb[0][row * kMfVP + k] = row < N ? (AT)rin[vi(row, k)] : AT(0);
+    vb[2][row * kMfVP + k] = row + 64 < N ? (AT)rin[vi(row + 64, k)] : AT(0);
+  }
+  __syncthreads();
+
+  // ---- forward sweep: vb[0] = t_b, vb[1] = y_b, vb[2] = u_{b+1} ----
+  for (int b = 0; b < NB; ++b) {
+    const int j0 = 64 * b;
+    const AT* Tb = tile + (b & 1) * CH;        // block b's rows
+    const AT* Tn = tile + (1 - (b & 1)) * CH;  // block b + 1's rows
+    AT rf[4], dvl[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      rf[v] = ldr(j0 + 128 + drow(v));
+      dvl[v] = dv[j0 + drow(v)];
+    }
+    const int ii = 16 * w + li;
+    V acc;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] = vb[0][drow(v) * kMfVP + li];
+    acc = mf_pass(
+        acc, [&](int kk) { const int jj = 4 * kk + lk; return ii > jj ? Tb[jj * PITCH + ii] : AT(0); },
+        [&](int kk) { return vb[0][(4 * kk + lk) * kMfVP + li]; });
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      vb[1][drow(v) * kMfVP + li] = acc[v];
+      const int row = j0 + drow(v);
+      if (row < N) out[vi(row, li)] = (double)(acc[v] * dvl[v]);
+    }
+    __syncthreads();  // y complete; every wave is done reading t_b
+    V an, af;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      an[v] = vb[2][drow(v) * kMfVP + li];
+      af[v] = rf[v];
+    }
+    an = mf_pass(
+        an, [&](int kk) { const int jj = 4 * kk + lk; return -Tn[jj * PITCH + ii]; },
+        [&](int kk) { return vb[1][(4 * kk + lk) * kMfVP + li]; });
+    af = mf_pass(
+        af, [&](int kk) { const int jj = 4 * kk + lk; return ii <= jj ? -Tb[jj * PITCH + ii] : AT(0); },
+        [&](int kk) { return vb[1][(4 * kk + lk) * kMfVP + li]; });
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      vb[0][drow(v) * kMfVP + li] = an[v];
+      vb[2][drow(v) * kMfVP + li] = af[v];
+    }
+    __syncthreads();  // every wave is done with tile b and with y_b
+    if (b + 1 < NB) {
+      tile_store();
+      if (b + 2 < NB) tile_load(b + 2);
+      __syncthreads();
+    }
+  }
+
+  // ---- backward sweep: tile NB-1 is still in LDS ----
+  if (NB > 1) tile_load(NB - 2);
+  int i1 = 0, i2 = 1, is = 2;  // buffers of x_{b+1}, x_{b+2}, s
+  for (int e = threadIdx.x; e < 64 * NT; e += NTHR) {
+    vb[0][(e / NT) * kMfVP + e % NT] = AT(0);
+    vb[1][(e / NT) * kMfVP + e % NT] = AT(0);
+  }
+  __syncthreads();
+  double rz = 0.0, qz = 0.0;  // column li of this lane's rows
+  for (int b = NB - 1; b >= 0; --b) {
+    const int j0 = 64 * b;
+    const AT* Tb = tile + (b & 1) * CH;
+    const AT* Tn = tile + (1 - (b & 1)) * CH;
+    AT vv[4];
+    double rp[4], qp[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = j0 + drow(v);
+      const bool ok = row < N;
+      vv[v] = ok ? (AT)out[vi(row, li)] : AT(0);
+      rp[v] = (ok && mode == 2) ? rin[vi(row, li)] : 0.0;
+      qp[v] = (ok && mode == 2) ? qv[vi(row, li)] : 0.0;
+    }
+    constexpr int NPA = 8;  // slots 0..31 fetched ahead, the rest when used
+    const int ra = j0 + 16 * w + li;
+    AT pa[NPA];
+#pragma unroll
+    for (int c = 0; c < NPA; ++c) {
+      const int q = 4 * c + lk;
+      pa[c] = (q < ns && ra < N) ? (AT)P[(size_t)q * N + ra] : AT(0);
+    }
+    const int ii = 16 * w + li;  // output row ii (a column of the tile)
+    const AT* x1 = vb[i1];
+    const AT* x2 = vb[i2];
+    V acc;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] = vv[v];
+    acc = mf_pass(
+        acc, [&](int kk) { const int jj = 4 * kk + lk; return -Tn[ii * PITCH + jj]; },
+        [&](int kk) { return x1[(4 * kk + lk) * kMfVP + li]; });
+    acc = mf_pass(
+        acc, [&](int kk) { const int jj = 4 * kk + lk; return jj <= ii ? -Tb[ii * PITCH + jj] : AT(0); },
+        [&](int kk) { return x2[(4 * kk + lk) * kMfVP + li]; });
+    AT* sv = vb[is];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sv[drow(v) * kMfVP + li] = acc[v];
+    __syncthreads();  // s complete; every wave is done reading x_{b+2}
+    acc = mf_pass(
+        acc, [&](int kk) { const int jj = 4 * kk + lk; return jj > ii ? Tb[ii * PITCH + jj] : AT(0); },
+        [&](int kk) { return sv[(4 * kk + lk) * kMfVP + li]; });
+    AT* xb = vb[i2];  // x_b over x_{b+2}
+#pragma unroll
+    for (int v = 0; v < 4; ++v) xb[drow(v) * kMfVP + li] = acc[v];
+#pragma unroll
+    for (int c = 0; c < NPA; ++c) {
+      if (4 * c >= ns) break;  // uniform
+      const int q = 4 * c + lk;
+      const AT e = q < ns ? eta_s[q * NT + li] : AT(0);
+      acc = mf4(pa[c], e, acc);
+    }
+    for (int c = NPA; 4 * c < ns; ++c) {
+      const int q = 4 * c + lk;
+      const AT av = (q < ns && ra < N) ? (AT)P[(size_t)q * N + ra] : AT(0);
+      const AT e = q < ns ? eta_s[q * NT + li] : AT(0);
+      acc = mf4(av, e, acc);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = j0 + drow(v);
+      if (row < N) {
+        const double zv = (double)acc[v];
+        out[vi(row, li)] = zv;
+        rz = fma(rp[v], zv, rz);
+        qz = fma(qp[v], zv, qz);
+      }
+    }
+    {  // x_b becomes x_{b+1} of the next step, x_{b+1} its x_{b+2}
+      const int t1 = i1;
+      i1 = i2;
+      i2 = t1;
+    }
+    __syncthreads();  // every wave is done with tile b, s and x_b
+    if (b > 0) {
+      tile_store();
+      if (b - 2 >= 0) tile_load(b - 2);
+      __syncthreads();
+    }
+  }
+
+  if (mode != 2) return;
+  rz += __shfl_xor(rz, 16, 64);
+  rz += __shfl_xor(rz, 32, 64);
+  qz += __shfl_xor(qz, 16, 64);
+  qz += __shfl_xor(qz, 32, 64);
+  if (lane < 16) {
+    dots[w][lane] = rz;
+    dots[w][NT + lane] = qz;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * NT) {
+    double a = 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a += dots[u][threadIdx.x];
+    partial[(size_t)(blk_off + blockIdx.x) * 2 * NT + threadIdx.x] = a;
+  }
+}
+
 // MBFs: one wave per (subdomain, slot): rhs = -B_s psi_n scattered from the
 // boundary weights, then the two sweeps in place.
 template <typename FT, int C>
@@ -1325,21 +1569,20 @@ template <typename FT, int NT, int I>
 hipError_t localt_shape(DeviceState& d, const double* r, double* z, const double* eta, int mode,
                         int init, hipStream_t st) {
   using IT = typename AccT<FT>::T;
-  unsigned off = 0;
-  int first_bk = -1, last_bk = -1;  // buckets launched first and last
-  for (int bk = 0; bk < 2; ++bk)
-    if (!d.bucket_sub[bk].empty()) {
-      if (first_bk < 0) first_bk = bk;
-      last_bk = bk;
-    }
-  for (int bk = 0; bk < 2; ++bk) {
-    const int nb = (int)d.bucket_sub[bk].size();
-    if (!nb) continue;
+  const int nb0 = (int)d.bucket_sub[0].size(), nb1 = (int)d.bucket_sub[1].size();
+  // With both window buckets populated, the window-128 bucket (few, long
+  // workgroups) runs on a second stream beside the window-64 one: a fork and
+  // a join on events, which graph capture records as two parallel branches.
+  // A profiled solve keeps the two launches in order on one stream.
+  const bool fork = nb0 > 0 && nb1 > 0 && d.side && !d.prof_ev[0] && !d.prof_ev[1];
+  auto launch_bucket = [&](int bk, hipStream_t s, bool first, bool last) {
+    const int nb = bk == 0 ? nb0 : nb1;
+    const unsigned off = bk == 0 ? 0u : (unsigned)nb0;  // rows of the partials
     // bucket 0 lists 0 .. m-1 in order when bucket 1 is empty: the kernel
     // then takes its subdomain from blockIdx.x (one dependent load less)
-    const int32_t* subs_arg = (bk == 0 && d.bucket_sub[1].empty()) ? nullptr : d.d_bucket_sub[bk];
+    const int32_t* subs_arg = (bk == 0 && nb1 == 0) ? nullptr : d.d_bucket_sub[bk];
     auto go = [&](auto kern, int threads) {
-      am_launch(d, bk == first_bk, bk == last_bk, kern, dim3(nb), dim3(threads), st,
+      am_launch(d, first, last, kern, dim3(nb), dim3(threads), s,
                 subs_arg, d.sub_ptr, d.roff, d.fac_off, (const FT*)d.Lc,
                 (const IT*)d.invd, r, z, mode, d.isub_ptr, d.isub_list, d.mbf_off, d.mbf, eta,
                 d.q, d.red.pd, off, d.fuse_eta, d.Sinv, (int)d.NL, d.ldS, d.bpart, d.red.pb, d.m,
@@ -1351,7 +1594,7 @@ hipError_t localt_shape(DeviceState& d, const double* r, double* z, const double
       if constexpr (NT == 16) {
         if (!d.fuse_eta) {
           mf = true;
-          am_launch(d, bk == first_bk, bk == last_bk, k_localt_mf<FT, 16>, dim3(nb), dim3(256), st,
+          am_launch(d, first, last, k_localt_mf<FT, 16>, dim3(nb), dim3(256), s,
                     d.d_bucket_sub[bk], d.sub_ptr, d.roff, d.fac_off, (const FT*)d.Lc,
                     (const IT*)d.invd, r, z, mode, d.isub_ptr, d.isub_list, d.mbf_off, d.mbf,
                     eta, d.q, d.red.pd, off, d.shared, d.n);
@@ -1360,9 +1603,30 @@ hipError_t localt_shape(DeviceState& d, const double* r, double* z, const double
       if (!mf) go(k_localt<FT, 1, NT, S::G, S::W>, 64 * S::G * S::W);
     } else {
       using S = TileAt<FT, 2, NT, I>;
-      go(k_localt<FT, 2, NT, S::G, S::W>, 64 * S::G * S::W);
+      bool mf = false;
+      if constexpr (NT == 16) {
+        if (!d.fuse_eta) {
+          mf = true;
+          am_launch(d, first, last, k_localt_mf2<FT, 16>, dim3(nb), dim3(256), s,
+                    d.d_bucket_sub[bk], d.sub_ptr, d.roff, d.fac_off, (const FT*)d.Lc,
+                    (const IT*)d.invd, r, z, mode, d.isub_ptr, d.isub_list, d.mbf_off, d.mbf,
+                    eta, d.q, d.red.pd, off, d.shared, d.n);
+        }
+      }
+      if (!mf) go(k_localt<FT, 2, NT, S::G, S::W>, 64 * S::G * S::W);
     }
-    off += nb;
+  };
+  if (fork) {
+    hipError_t e = hipEventRecord(d.ev_fork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(d.side, d.ev_fork, 0);
+    if (e != hipSuccess) return e;
+    launch_bucket(1, d.side, false, false);
+    if ((e = hipEventRecord(d.ev_join, d.side)) != hipSuccess) return e;
+    launch_bucket(0, st, false, false);
+    if ((e = hipStreamWaitEvent(st, d.ev_join, 0)) != hipSuccess) return e;
+  } else {
+    if (nb0 > 0) launch_bucket(0, st, true, nb1 == 0);
+    if (nb1 > 0) launch_bucket(1, st, nb0 == 0, true);
   }
   return hipGetLastError();
 }
