@@ -53,7 +53,8 @@ def traffic_record(prec, config, tile_choice):
     """HBM bytes per launch of the local kernel from committed rocprofv3
     counter runs, valid only while the kernel source is unchanged and for the
     wave layout the counters were taken with (the runs pin it with
-    ALGMORTAR_TILE; the record stores it as "tile_choice")."""
+    ALGMORTAR_TILE; the record keeps one entry per layout measured, under
+    "per_tile_choice")."""
     path = os.path.join(ROOT, "profiles", f"k_local_{config}_{prec}_traffic.json")
     if not os.path.exists(path):
         return None
@@ -61,9 +62,8 @@ def traffic_record(prec, config, tile_choice):
     src = open(os.path.join(ROOT, "paper_2607_22905_amd", "csrc", "local_kernels.h"), "rb").read()
     if rec.get("local_kernels_sha256") != hashlib.sha256(src).hexdigest():
         return None
-    if rec.get("tile_choice") != tile_choice:
-        return None
-    return rec.get("hbm_bytes_per_launch")
+    ent = rec.get("per_tile_choice", {}).get(str(tile_choice))
+    return None if ent is None else ent.get("hbm_bytes_per_launch")
 
 
 def gradient_timing(P, part, m, steps):

@@ -343,7 +343,9 @@ am_status algmortar_time_kernel(am_handle h, int32_t kernel, int32_t nrhs, int32
  * factor precision, interface form and right-hand-side count, and the
  * choice) and read back by later handles and processes, which then use the
  * recorded layout without timing (us holds zeros): the same results as the
- * process that timed it. */
+ * process that timed it.  16 right-hand sides with the interface solve as
+ * its own launches run matrix-core kernels of a single layout: choice 0,
+ * ncand 1, nothing timed. */
 am_status algmortar_tile_choice(am_handle h, int32_t nrhs, int32_t* choice, int32_t* ncand,
                                 double* us);
 

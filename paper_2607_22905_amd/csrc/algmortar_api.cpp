@@ -869,6 +869,13 @@ static am_status autotune_tiles(am_handle h, int nr) {
   const int slot = tile_slot(nr);
   if (d.tile_cand[slot] >= 0) return AM_OK;
   const int nc = tile_candidates(nr);
+  // 16 right-hand sides with the interface solve as its own launches run the
+  // matrix-core kernels in both window buckets, which have one layout: nothing
+  // to choose
+  if (nr == 16 && !d.fuse_eta) {
+    d.tile_cand[slot] = 0;
+    return AM_OK;
+  }
   // ALGMORTAR_TILE=c pins candidate c (clamped to the list): the layouts
   // sum the waves' partial vectors in different orders, so results of
   // handles (or processes) whose timings chose differently can differ in
@@ -944,7 +951,7 @@ am_status algmortar_tile_choice(am_handle h, int32_t nrhs, int32_t* choice, int3
   if (s != AM_OK) return s;
   const int slot = tile_slot(nr);
   *choice = h->d.tile_cand[slot];
-  *ncand = tile_candidates(nr);
+  *ncand = (nr == 16 && !h->d.fuse_eta) ? 1 : tile_candidates(nr);
   if (us)
     for (int c = 0; c < *ncand; ++c) us[c] = h->d.tile_us[slot][c];
   return AM_OK;
