@@ -1,6 +1,8 @@
 """The autotuner's persisted choices (ALGMORTAR_AUTOTUNE_CACHE): two fresh
-processes solve the same 16-column system on the bisection grid (three
-candidate wave layouts); the first times the layouts and records its choice,
+processes solve the same 8-column system on the bisection grid (three
+candidate wave layouts of the vector-unit tile kernel; 16 columns run the
+matrix-core kernels, which have one layout); the first times the layouts and
+records its choice,
 the second reads it and times nothing; their solutions are equal bit for
 bit (the layouts differ in the order partial vectors are added, so without
 the record two processes could differ in the last bits)."""
@@ -22,10 +24,10 @@ import numpy as np, torch
 import paper_2607_22905_amd as am
 from tests.test_gpu_parity import _case
 A, part, m, b = _case("bisect")
-h = am.AlgMortar(A, part, m, max_nrhs=16)
-R = np.random.default_rng(5).standard_normal((16, A.n))
+h = am.AlgMortar(A, part, m, max_nrhs=8)
+R = np.random.default_rng(5).standard_normal((8, A.n))
 X, info, _ = h.pcg(torch.as_tensor(R, device="cuda:0"), 1e-10)
-ch, us = h.tile_choice(16)
+ch, us = h.tile_choice(8)
 np.save({out!r}, X.cpu().numpy())
 print(json.dumps({{"choice": ch, "us": us}}))
 h.close()
@@ -52,3 +54,17 @@ def test_two_processes_bitwise_equal(tmp_path):
     x2, i2 = _run(tmp_path, "second", cache)
     assert i2["choice"] == i1["choice"] and all(u == 0 for u in i2["us"])
     assert np.array_equal(x1, x2)
+
+
+def test_sixteen_columns_one_layout():
+    """16 columns with the interface solve as its own launches run the
+    matrix-core kernels in both window buckets: one layout, nothing timed."""
+    import torch  # noqa: F401
+    sys.path.insert(0, ROOT)
+    import paper_2607_22905_amd as am
+    from tests.test_gpu_parity import _case
+    A, part, m, b = _case("bisect")
+    h = am.AlgMortar(A, part, m, max_nrhs=16, separate_iface=True)
+    ch, us = h.tile_choice(16)
+    assert ch == 0 and us == [0.0]
+    h.close()
