@@ -318,9 +318,6 @@ __global__ __launch_bounds__(256) void k_update_xr(
   // registers of four (more workgroups resident where there are many)
   constexpr int RPT = 2;
   constexpr int QB = KG <= 2 ? 8 : 4;
-  // with 8 or more columns the interface partials are formed after the rows,
-  // one slot per wave at a time (no block-wide sums per group of slots)
-  constexpr bool kWaveSlots = NT >= 8;
   __shared__ double lds[4 * 32];
   const int s = blockIdx.x / TR, g = blockIdx.x % TR, k0 = g * KG;
   const int done_flag = *(volatile const int32_t*)&sh->all_done;
@@ -367,7 +364,7 @@ __global__ __launch_bounds__(256) void k_update_xr(
       }
 #pragma unroll
       for (int qq = 0; qq < QB; ++qq)
-        ph[u][qq] = (!kWaveSlots && ok && qq < ns) ? P[(size_t)qq * N + row] : 0.0;
+        ph[u][qq] = (ok && qq < ns) ? P[(size_t)qq * N + row] : 0.0;
     }
     if (!have_alpha) {
       have_alpha = true;
@@ -418,7 +415,7 @@ __global__ __launch_bounds__(256) void k_update_xr(
         for (int qq = 0; qq < QB; ++qq) vb[qq * KG + k] = fma(ph[u][qq], rn, vb[qq * KG + k]);
       }
     }
-    if (!kWaveSlots && N <= RPT * 256) {
+    if (N <= RPT * 256) {
       // single pass: the first QB slots from registers, the rest re-read
       block_sum<QB * KG>(vb, lds);
       if (tid == 0)
@@ -453,26 +450,7 @@ __global__ __launch_bounds__(256) void k_update_xr(
       }
     }
   }
-  if (kWaveSlots) {
-    __syncthreads();  // the new r of the subdomain is written
-    const int lane = tid & 63, wv = tid >> 6, nwv = blockDim.x >> 6;
-    for (int qq = wv; qq < ns; qq += nwv) {
-      double a[KG];
-#pragma unroll
-      for (int k = 0; k < KG; ++k) a[k] = 0.0;
-#pragma unroll 4
-      for (int row = lane; row < N; row += 64) {
-        const double phv = P[(size_t)qq * N + row];
-#pragma unroll
-        for (int k = 0; k < KG; ++k) a[k] = fma(phv, r[vix<NT>(n, base + row, k0 + k)], a[k]);
-      }
-#pragma unroll
-      for (int k = 0; k < KG; ++k) {
-        const double t = wave_sum(a[k]);
-        if (lane == 0) bpart[(size_t)bdst[i0 + qq] * NT + k0 + k] = 0.25 * t;
-      }
-    }
-  } else if (N > RPT * 256) {
+  if (N > RPT * 256) {
     __syncthreads();
     bpart_sub_g<NT, KG>(s, k0, n, sub_ptr, isub_ptr, mbf_off, mbf, bdst, r, bpart, lds);
   }
