@@ -198,17 +198,22 @@ def cpu_baseline(config, P, its_to_converge, smooth=None, theta=None):
 def precision_forms(P, part, m, b, x64, args, v64, its64):
     """The precision form on the same workload: FP32 and BF16 local factors
     (BF16: bf16 storage, fp32 arithmetic), FP64 interface solve, dots and
-    residuals; each timed like the FP64 run.  Reports solves/s, the speedup
-    over FP64, iterations (and their change) and the relative L2 distance of
-    the solution from the FP64 one (both at the workload's tolerance)."""
+    residuals; with 16 right-hand sides also BF16 x BF16 products on the
+    matrix cores (block vectors rounded to BF16, FP32 accumulation); each
+    timed like the FP64 run.  Reports solves/s, the speedup over FP64,
+    iterations (and their change) and the relative L2 distance of the
+    solution from the FP64 one (both at the workload's tolerance)."""
     import numpy as np
     import torch
 
     import paper_2607_22905_amd as am
     res = {}
     nrhs = P.nrhs
-    for prec in ("fp32", "bf16"):
-        h = am.AlgMortar(P.A, part, m, prec=prec, graph=not args.no_graph, max_nrhs=nrhs)
+    forms = [("fp32", "fp32", {}), ("bf16", "bf16", {})]
+    if nrhs == 16:
+        forms.append(("bf16_products", "bf16", {"bf16_products": True}))
+    for name, prec, kw in forms:
+        h = am.AlgMortar(P.A, part, m, prec=prec, graph=not args.no_graph, max_nrhs=nrhs, **kw)
         x = torch.empty_like(b)
         for _ in range(args.warmup):
             h.pcg(b, P.tol, out=x)
@@ -221,13 +226,13 @@ def precision_forms(P, part, m, b, x64, args, v64, its64):
         its = max(i["iterations"] for i in info)
         v = args.steps * nrhs / el
         err = float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))
-        res[prec] = {"value": v, "unit": "solves/s", "speedup_vs_fp64": v / v64,
+        res[name] = {"value": v, "unit": "solves/s", "speedup_vs_fp64": v / v64,
                      "ms_per_step": el / args.steps * 1e3, "iterations": its,
                      "iteration_change_vs_fp64": its - its64,
                      "true_rel_res": max(i["true_rel_res"] for i in info),
                      "rel_l2_vs_fp64_solution": err,
                      "local_tile_autotune": h.tile_choice(nrhs)[0]}
-        log(f"bench: {prec} local factors: {v:.1f} solves/s ({v / v64:.2f}x FP64), {its} iterations")
+        log(f"bench: {name} local factors: {v:.1f} solves/s ({v / v64:.2f}x FP64), {its} iterations")
         h.close()
     return res
 

@@ -18,6 +18,7 @@ AM_FLAG_NO_GRAPH = 1
 AM_FLAG_SEPARATE_IFACE = 2
 AM_FLAG_DENSE_IFACE = 4
 AM_FLAG_INEXACT_IFACE = 8
+AM_FLAG_BF16_PRODUCTS = 16
 
 
 class AmCsr(ctypes.Structure):

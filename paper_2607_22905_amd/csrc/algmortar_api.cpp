@@ -536,6 +536,7 @@ static am_status setup_impl(const am_csr* A, const int32_t* part, int32_t nparts
   // (at least 8 KB for every factor precision and window)
   if ((int64_t)lp.max_ni * pow2_at_least(std::max(opt.max_nrhs, 1)) * 8 * 8 > 8192) d.fuse_eta = 0;
   if (opt.flags & (AM_FLAG_SEPARATE_IFACE | AM_FLAG_INEXACT_IFACE)) d.fuse_eta = 0;
+  d.bf16_ops = (opt.flags & AM_FLAG_BF16_PRODUCTS) && d.prec == AM_BF16 ? 1 : 0;
   const bool use_ix = !plain && d.NL > 0 && (opt.flags & AM_FLAG_INEXACT_IFACE);
   for (int32_t s2 = 0; s2 < st.m; ++s2)
     d.max_np = std::max<int32_t>(d.max_np, (int32_t)(lp.roff[s2 + 1] - lp.roff[s2]));

@@ -133,6 +133,7 @@ struct DeviceState {
   int32_t ldS = 0;  // padded interface dimension (multiple of kTile)
   int32_t fuse_eta = 0;  // local kernel computes its own rows of eta = S^{-1} b
   int32_t plain = 0;     // factors are the plain diagonal blocks A_ii (block Jacobi)
+  int32_t bf16_ops = 0;  // 16-RHS matrix-core sweeps: BF16 x BF16 products (AM_FLAG_BF16_PRODUCTS)
   int32_t max_nrhs = 1;
   int32_t max_np = 0;       // largest padded subdomain row count
   // wave layout of the tile kernel chosen by the autotuner per right-hand-side

@@ -19,6 +19,8 @@
 // per row between the two sweeps.  Padding rows have a zero factor and
 // dinv = 1.
 #pragma once
+#include <type_traits>
+
 #include "am_common.h"
 
 namespace am {
@@ -913,32 +915,63 @@ __device__ __forceinline__ am_mf_f4 mf4(float a, float b, am_mf_f4 c) {
 }
 
 
-// acc += sum over the 64 columns of A[rows][col] B[col][.] for a 16-row strip:
-// the 16 operand pairs are read from LDS first, then four independent chains
-// of four products (columns 4 kk + lk with kk = c mod 4 in chain c) are
-// added in chain order.
-template <typename V, typename AF, typename BF>
+// acc += sum over the 64 columns jj of A[rows][jj] B[jj][.] for a 16-row
+// strip, afn(c, m) and bfn(c, m) giving this lane's operands at column
+// jj = c + m lk (lk = lane / 16, held by the caller), c and m constants of
+// the unrolled loop.  FP64 / FP32 (16x16x4 products): lane holds column 4 kk + lk of
+// step kk; the 16 operand pairs are read from LDS first, then four
+// independent chains of four products (kk = c mod 4 in chain c) are added in
+// chain order.  BF16 (BFOP, FP32 arithmetic type only): four 16x16x16
+// products, lane holding columns 16 c + 4 lk .. 16 c + 4 lk + 3 of step c,
+// both operands rounded to BF16 (the factor values are BF16 already), two
+// chains added in order.
+__device__ __forceinline__ short am_bf16_rne(float x) {
+  uint32_t u = __builtin_bit_cast(uint32_t, x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+typedef short am_mf_s4 __attribute__((ext_vector_type(4)));
+template <bool BFOP, typename V, typename AF, typename BF>
 __device__ __forceinline__ V mf_pass(V acc, AF&& afn, BF&& bfn) {
-  using AT = decltype(afn(0));
-  V c[4];
-  c[0] = acc;
+  using AT = decltype(afn(0, 0));
+  if constexpr (BFOP) {
+    static_assert(sizeof(AT) == 4, "BF16 products: FP32 arithmetic type");
+    V c[2];
+    c[0] = acc;
+    c[1] = V{0, 0, 0, 0};
+    am_mf_s4 a[4], b[4];
 #pragma unroll
-  for (int t = 1; t < 4; ++t) c[t] = V{0, 0, 0, 0};
+    for (int st = 0; st < 4; ++st)
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {  // two halves of 8 operand pairs (registers)
-    AT a[8], b[8];
+      for (int t = 0; t < 4; ++t) {
+        a[st][t] = am_bf16_rne(afn(16 * st + t, 4));
+        b[st][t] = am_bf16_rne(bfn(16 * st + t, 4));
+      }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      a[u] = afn(8 * h + u);
-      b[u] = bfn(8 * h + u);
+    for (int st = 0; st < 4; ++st)
+      c[st % 2] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[st], b[st], c[st % 2], 0, 0, 0);
+    return c[0] + c[1];
+  } else {
+    V c[4];
+    c[0] = acc;
+#pragma unroll
+    for (int t = 1; t < 4; ++t) c[t] = V{0, 0, 0, 0};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {  // two halves of 8 operand pairs (registers)
+      AT a[8], b[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        a[u] = afn(4 * (8 * h + u), 1);
+        b[u] = bfn(4 * (8 * h + u), 1);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) c[u % 4] = mf4(a[u], b[u], c[u % 4]);
     }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) c[u % 4] = mf4(a[u], b[u], c[u % 4]);
+    return (c[0] + c[1]) + (c[2] + c[3]);
   }
-  return (c[0] + c[1]) + (c[2] + c[3]);
 }
 
-template <typename FT, int NT>
+template <typename FT, int NT, bool BFOP = false>
 __global__ __launch_bounds__(256) void k_localt_mf(
     const int32_t* __restrict__ subs, const int64_t* __restrict__ sub_ptr,
     const int64_t* __restrict__ roff, const int64_t* __restrict__ fac_off,
@@ -1028,9 +1061,9 @@ __global__ __launch_bounds__(256) void k_localt_mf(
     for (int v = 0; v < 4; ++v) acc[v] = vb[0][drow(v) * kMfVP + li];
     {
       const int ii = 16 * w + li;
-      acc = mf_pass(
-          acc, [&](int kk) { const int jj = 4 * kk + lk; return ii > jj ? T[jj * PITCH + ii] : AT(0); },
-          [&](int kk) { return vb[0][(4 * kk + lk) * kMfVP + li]; });
+      acc = mf_pass<BFOP>(
+          acc, [&](int c, int m) { const int jj = c + m * lk; return ii > jj ? T[jj * PITCH + ii] : AT(0); },
+          [&](int c, int m) { const int jj = c + m * lk; return vb[0][jj * kMfVP + li]; });
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -1044,9 +1077,9 @@ __global__ __launch_bounds__(256) void k_localt_mf(
     for (int v = 0; v < 4; ++v) acc[v] = rn[v];
     {
       const int ii = 16 * w + li;
-      acc = mf_pass(
-          acc, [&](int kk) { const int jj = 4 * kk + lk; return ii <= jj ? -T[jj * PITCH + ii] : AT(0); },
-          [&](int kk) { return vb[1][(4 * kk + lk) * kMfVP + li]; });
+      acc = mf_pass<BFOP>(
+          acc, [&](int c, int m) { const int jj = c + m * lk; return ii <= jj ? -T[jj * PITCH + ii] : AT(0); },
+          [&](int c, int m) { const int jj = c + m * lk; return vb[1][jj * kMfVP + li]; });
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) vb[0][drow(v) * kMfVP + li] = acc[v];
@@ -1098,9 +1131,9 @@ __global__ __launch_bounds__(256) void k_localt_mf(
     for (int v = 0; v < 4; ++v) acc[v] = vv[v];
     {
       const int ii = 16 * w + li;  // output row ii, tile row jj
-      acc = mf_pass(
-          acc, [&](int kk) { const int jj = 4 * kk + lk; return jj <= ii ? -T[ii * PITCH + jj] : AT(0); },
-          [&](int kk) { return vb[1][(4 * kk + lk) * kMfVP + li]; });
+      acc = mf_pass<BFOP>(
+          acc, [&](int c, int m) { const int jj = c + m * lk; return jj <= ii ? -T[ii * PITCH + jj] : AT(0); },
+          [&](int c, int m) { const int jj = c + m * lk; return vb[1][jj * kMfVP + li]; });
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) vb[0][drow(v) * kMfVP + li] = acc[v];
@@ -1108,9 +1141,9 @@ __global__ __launch_bounds__(256) void k_localt_mf(
     // pass B: x = s + Nlow^T s
     {
       const int ii = 16 * w + li;
-      acc = mf_pass(
-          acc, [&](int kk) { const int jj = 4 * kk + lk; return jj > ii ? T[ii * PITCH + jj] : AT(0); },
-          [&](int kk) { return vb[0][(4 * kk + lk) * kMfVP + li]; });
+      acc = mf_pass<BFOP>(
+          acc, [&](int c, int m) { const int jj = c + m * lk; return jj > ii ? T[ii * PITCH + jj] : AT(0); },
+          [&](int c, int m) { const int jj = c + m * lk; return vb[0][jj * kMfVP + li]; });
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) vb[1][drow(v) * kMfVP + li] = acc[v];
@@ -1186,7 +1219,7 @@ __global__ __launch_bounds__(256) void k_localt_mf(
 // x_{b+2}, s, with x_b written over x_{b+2}), with one tile buffer of two
 // chunks: about 100 KB, so that a workgroup of the window-64 kernel still
 // fits beside it on a CU (the two buckets run side by side).
-template <typename FT, int NT>
+template <typename FT, int NT, bool BFOP = false>
 __global__ __launch_bounds__(256) void k_localt_mf2(
     const int32_t* __restrict__ subs, const int64_t* __restrict__ sub_ptr,
     const int64_t* __restrict__ roff, const int64_t* __restrict__ fac_off,
@@ -1275,9 +1308,9 @@ __global__ __launch_bounds__(256) void k_localt_mf2(
     V acc;
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[v] = vb[0][drow(v) * kMfVP + li];
-    acc = mf_pass(
-        acc, [&](int kk) { const int jj = 4 * kk + lk; return ii > jj ? Tb[jj * PITCH + ii] : AT(0); },
-        [&](int kk) { return vb[0][(4 * kk + lk) * kMfVP + li]; });
+    acc = mf_pass<BFOP>(
+        acc, [&](int c, int m) { const int jj = c + m * lk; return ii > jj ? Tb[jj * PITCH + ii] : AT(0); },
+        [&](int c, int m) { const int jj = c + m * lk; return vb[0][jj * kMfVP + li]; });
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       vb[1][drow(v) * kMfVP + li] = acc[v];
@@ -1291,12 +1324,12 @@ __global__ __launch_bounds__(256) void k_localt_mf2(
       an[v] = vb[2][drow(v) * kMfVP + li];
       af[v] = rf[v];
     }
-    an = mf_pass(
-        an, [&](int kk) { const int jj = 4 * kk + lk; return -Tn[jj * PITCH + ii]; },
-        [&](int kk) { return vb[1][(4 * kk + lk) * kMfVP + li]; });
-    af = mf_pass(
-        af, [&](int kk) { const int jj = 4 * kk + lk; return ii <= jj ? -Tb[jj * PITCH + ii] : AT(0); },
-        [&](int kk) { return vb[1][(4 * kk + lk) * kMfVP + li]; });
+    an = mf_pass<BFOP>(
+        an, [&](int c, int m) { const int jj = c + m * lk; return -Tn[jj * PITCH + ii]; },
+        [&](int c, int m) { const int jj = c + m * lk; return vb[1][jj * kMfVP + li]; });
+    af = mf_pass<BFOP>(
+        af, [&](int c, int m) { const int jj = c + m * lk; return ii <= jj ? -Tb[jj * PITCH + ii] : AT(0); },
+        [&](int c, int m) { const int jj = c + m * lk; return vb[1][jj * kMfVP + li]; });
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       vb[0][drow(v) * kMfVP + li] = an[v];
@@ -1347,19 +1380,19 @@ __global__ __launch_bounds__(256) void k_localt_mf2(
     V acc;
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[v] = vv[v];
-    acc = mf_pass(
-        acc, [&](int kk) { const int jj = 4 * kk + lk; return -Tn[ii * PITCH + jj]; },
-        [&](int kk) { return x1[(4 * kk + lk) * kMfVP + li]; });
-    acc = mf_pass(
-        acc, [&](int kk) { const int jj = 4 * kk + lk; return jj <= ii ? -Tb[ii * PITCH + jj] : AT(0); },
-        [&](int kk) { return x2[(4 * kk + lk) * kMfVP + li]; });
+    acc = mf_pass<BFOP>(
+        acc, [&](int c, int m) { const int jj = c + m * lk; return -Tn[ii * PITCH + jj]; },
+        [&](int c, int m) { const int jj = c + m * lk; return x1[jj * kMfVP + li]; });
+    acc = mf_pass<BFOP>(
+        acc, [&](int c, int m) { const int jj = c + m * lk; return jj <= ii ? -Tb[ii * PITCH + jj] : AT(0); },
+        [&](int c, int m) { const int jj = c + m * lk; return x2[jj * kMfVP + li]; });
     AT* sv = vb[is];
 #pragma unroll
     for (int v = 0; v < 4; ++v) sv[drow(v) * kMfVP + li] = acc[v];
     __syncthreads();  // s complete; every wave is done reading x_{b+2}
-    acc = mf_pass(
-        acc, [&](int kk) { const int jj = 4 * kk + lk; return jj > ii ? Tb[ii * PITCH + jj] : AT(0); },
-        [&](int kk) { return sv[(4 * kk + lk) * kMfVP + li]; });
+    acc = mf_pass<BFOP>(
+        acc, [&](int c, int m) { const int jj = c + m * lk; return jj > ii ? Tb[ii * PITCH + jj] : AT(0); },
+        [&](int c, int m) { const int jj = c + m * lk; return sv[jj * kMfVP + li]; });
     AT* xb = vb[i2];  // x_b over x_{b+2}
 #pragma unroll
     for (int v = 0; v < 4; ++v) xb[drow(v) * kMfVP + li] = acc[v];
@@ -1588,16 +1621,23 @@ hipError_t localt_shape(DeviceState& d, const double* r, double* z, const double
                 d.q, d.red.pd, off, d.fuse_eta, d.Sinv, (int)d.NL, d.ldS, d.bpart, d.red.pb, d.m,
                 init, d.sc, d.shared, d.n);
     };
+    // the matrix-core kernels of 16 columns (BF16 x BF16 products on request)
+    auto go_mf = [&](auto kern) {
+      am_launch(d, first, last, kern, dim3(nb), dim3(256), s, d.d_bucket_sub[bk], d.sub_ptr,
+                d.roff, d.fac_off, (const FT*)d.Lc, (const IT*)d.invd, r, z, mode, d.isub_ptr,
+                d.isub_list, d.mbf_off, d.mbf, eta, d.q, d.red.pd, off, d.shared, d.n);
+    };
+    constexpr bool kBf = std::is_same<FT, bf16_t>::value;
     if (bk == 0) {
       using S = TileAt<FT, 1, NT, I>;
       bool mf = false;
       if constexpr (NT == 16) {
         if (!d.fuse_eta) {
           mf = true;
-          am_launch(d, first, last, k_localt_mf<FT, 16>, dim3(nb), dim3(256), s,
-                    d.d_bucket_sub[bk], d.sub_ptr, d.roff, d.fac_off, (const FT*)d.Lc,
-                    (const IT*)d.invd, r, z, mode, d.isub_ptr, d.isub_list, d.mbf_off, d.mbf,
-                    eta, d.q, d.red.pd, off, d.shared, d.n);
+          if (kBf && d.bf16_ops)
+            go_mf(k_localt_mf<FT, 16, kBf>);
+          else
+            go_mf(k_localt_mf<FT, 16, false>);
         }
       }
       if (!mf) go(k_localt<FT, 1, NT, S::G, S::W>, 64 * S::G * S::W);
@@ -1607,10 +1647,10 @@ hipError_t localt_shape(DeviceState& d, const double* r, double* z, const double
       if constexpr (NT == 16) {
         if (!d.fuse_eta) {
           mf = true;
-          am_launch(d, first, last, k_localt_mf2<FT, 16>, dim3(nb), dim3(256), s,
-                    d.d_bucket_sub[bk], d.sub_ptr, d.roff, d.fac_off, (const FT*)d.Lc,
-                    (const IT*)d.invd, r, z, mode, d.isub_ptr, d.isub_list, d.mbf_off, d.mbf,
-                    eta, d.q, d.red.pd, off, d.shared, d.n);
+          if (kBf && d.bf16_ops)
+            go_mf(k_localt_mf2<FT, 16, kBf>);
+          else
+            go_mf(k_localt_mf2<FT, 16, false>);
         }
       }
       if (!mf) go(k_localt<FT, 2, NT, S::G, S::W>, 64 * S::G * S::W);

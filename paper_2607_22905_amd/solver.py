@@ -130,7 +130,7 @@ class AlgMortar:
 
     def __init__(self, A, part, nparts, prec="fp64", mortar="interface", max_nrhs=1, device=0,
                  graph=True, stream=None, separate_iface=False, dense_iface=False,
-                 inexact_iface=False):
+                 inexact_iface=False, bf16_products=False):
         lib = load()
         s, keep = _csr(A)
         p = _np(part, np.int32)
@@ -139,7 +139,8 @@ class AlgMortar:
                         flags=(0 if graph else _lib.AM_FLAG_NO_GRAPH)
                         | (_lib.AM_FLAG_SEPARATE_IFACE if separate_iface else 0)
                         | (_lib.AM_FLAG_DENSE_IFACE if dense_iface else 0)
-                        | (_lib.AM_FLAG_INEXACT_IFACE if inexact_iface else 0))
+                        | (_lib.AM_FLAG_INEXACT_IFACE if inexact_iface else 0)
+                        | (_lib.AM_FLAG_BF16_PRODUCTS if bf16_products else 0))
         h = c_void_p()
         st = c_void_p(0) if stream is False else _stream(stream)
         check(lib.algmortar_setup(byref(s), _ptr(p), int(nparts), byref(opt), st, byref(h)))

@@ -394,6 +394,48 @@ def test_matrix_core_16_rhs_reduced_precision(prec):
     hm.close()
 
 
+def test_bf16_products_16_rhs():
+    """BF16 factors with BF16 x BF16 products on the matrix cores (block
+    vectors rounded to BF16, FP32 accumulation; AM_FLAG_BF16_PRODUCTS), 16
+    right-hand sides on the bisection grid, interface solve as its own
+    launches (windows 64 and 128).  The apply is a further perturbed AlgMortar:
+    within 0.05 of the oracle's FP64 apply, and at least 1e-5 (relative) from
+    the FP32-product form with the same factors (the flag is in effect; the
+    rounding of the factors to BF16 dominates both forms' distance from the
+    oracle, about 6e-3 here, so neither is always the closer one).  PCG
+    (flexible, FP64 outer loop) at tol 1e-10: columns 0, 5 and 15 within 1e-8
+    of the oracle's solutions, true residual <= 1e-9, iterations at most
+    twice the oracle's plus 10."""
+    A, part, m, b, ora = setup_case("bisect")
+    rng = np.random.default_rng(161)
+    n = A.n
+    R = rng.standard_normal((16, n))
+    Zo = np.stack([ora.apply(R[c]) for c in range(16)])
+    hb = am.AlgMortar(A, part, m, prec="bf16", max_nrhs=16, separate_iface=True, bf16_products=True)
+    hf = am.AlgMortar(A, part, m, prec="bf16", max_nrhs=16, separate_iface=True)
+    Zb = cpu(hb.apply(gpu(R)))
+    Zf = cpu(hf.apply(gpu(R)))
+    for c in range(16):
+        eb, ebf = rel(Zb[c], Zo[c]), rel(Zb[c], Zf[c])
+        assert eb <= 5e-2 and ebf >= 1e-5, (c, eb, ebf)
+    hf.close()
+    B = np.zeros((16, n))
+    wells = rng.choice(n, size=32, replace=False)
+    for c in range(16):
+        B[c, wells[2 * c]] += 1.0
+        B[c, wells[2 * c + 1]] -= 1.0
+    B[0] = b
+    X, infos, _ = hb.pcg(gpu(B), 1e-10)
+    X = cpu(X)
+    As = A.to_scipy()
+    for c in (0, 5, 15):
+        ref = pcg(lambda v: As @ v, B[c], ora.apply, 1e-10)
+        assert rel(X[c], ref.x) <= 1e-8
+        assert infos[c]["converged"] == 1 and infos[c]["true_rel_res"] <= 1e-9
+        assert infos[c]["iterations"] <= 2 * ref.iterations + 10
+    hb.close()
+
+
 @pytest.mark.parametrize("dense", [False, True])
 @pytest.mark.parametrize("name,max_nrhs", [("c1", 1), ("layered", 1), ("ragged3d", 2),
                                            ("bisect", 2), ("layered", 4), ("ragged3d", 16),
