@@ -140,6 +140,32 @@ def test_subdomain_with_100_basis_functions():
     assert e.value.status_name == "AM_ERR_UNSUPPORTED"
 
 
+@pytest.mark.parametrize("nrhs,separate", [(8, False), (16, True)])
+def test_subdomain_with_48_basis_functions_many_columns(nrhs, separate):
+    """One subdomain touching 48 basis functions (more than the 32 interface
+    slots the 8/16-column update keeps in registers, and than the 32 the
+    matrix-core reconstruction fetches ahead) with 8 and 16 columns: applies
+    of every column within 1e-12 of the oracle, PCG within 1e-8 of the oracle
+    with the iteration count within one."""
+    P, part, m = _comb(48)
+    ora = AlgMortarCPU(P.A, part)
+    assert int((np.asarray(ora.st.iface_ij) == 0).any(axis=1).sum()) == 48
+    h = am.AlgMortar(P.A, part, m, max_nrhs=nrhs, separate_iface=separate)
+    rng = np.random.default_rng(48)
+    R = rng.standard_normal((nrhs, P.n))
+    Z = cpu(h.apply(gpu(R)))
+    for c in range(nrhs):
+        assert rel(Z[c], ora.apply(R[c])) <= 1e-12, c
+    X, infos, _ = h.pcg(gpu(R), 1e-10)
+    X = cpu(X)
+    for c in (0, nrhs - 1):
+        res = pcg(lambda v: ora.As @ v, R[c], ora.apply, 1e-10)
+        assert infos[c]["converged"] == 1
+        assert abs(infos[c]["iterations"] - res.iterations) <= 1
+        assert rel(X[c], res.x) <= 1e-8
+    h.close()
+
+
 def test_setup_limits():
     P, part, m = _comb(130)
     with pytest.raises(AlgMortarError) as e:
