@@ -1557,8 +1557,8 @@ hipError_t invert_diag_t(DeviceState& d, hipStream_t st) {
 // right-hand-side count, the first being the default.
 template <int NT> struct TileCands;
 template <> struct TileCands<1> {
-  static constexpr int n = 2;
-  static constexpr int G[4] = {1, 1, 1, 1}, W[4] = {4, 2, 4, 4};
+  static constexpr int n = 3;
+  static constexpr int G[4] = {1, 1, 1, 1}, W[4] = {4, 2, 8, 4};
 };
 template <> struct TileCands<2> {
   static constexpr int n = 2;
