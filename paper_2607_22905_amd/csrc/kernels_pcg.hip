@@ -1,10 +1,13 @@
 // PCG kernels for gfx950 (Sec. 5: AlgMortar as the CG preconditioner; Sec. 7:
-// x0 = 0, relative residual stop).  One iteration is four launches:
-//   spmv_p   : beta from (r, z); p = z + beta p (ping-pong buffers), q = A p, (p, q)
-//   update_xr: alpha = (r, z)/(p, q); x += alpha p, r -= alpha q, ||r||^2; the
+// x0 = 0, relative residual stop).  One iteration is, in order:
+//   SpMV     : beta from (r, z); p = z + beta p (ping-pong buffers), q = A p, (p, q)
+//              (k_spmv_p with 1-4 columns, k_pcg_coef + k_spmv_sub with 8-16)
+//   update   : alpha = (r, z)/(p, q); x += alpha p, r -= alpha q, ||r||^2; the
 //              interface partial right-hand sides 1/4 phat^T r per (subdomain, slot)
-//   gemv     : stop test on ||r||; eta = S^{-1} b      (kernels_iface.hip)
-//   local    : z = A_i^{-1} r + sum eta_m phat^(m), (r, z), (q, z) (kernels_local.hip)
+//              (k_update_xr with 1-4 columns, k_pcg_coef + k_update_rows with 8-16)
+//   interface: stop test on ||r||; eta = S^{-1} b, where it is its own launches
+//              (kernels_nd.hip, kernels_iface.hip, kernels_inexact.hip)
+//   local    : z = A_i^{-1} r + sum eta_m phat^(m), (r, z), (q, z) (local_kernels.h)
 // Scalars stay on the device.  With up to four columns a launch that needs a
 // scalar folds the per-block partial sums of the launch that produced them,
 // in block order and identically in every workgroup (deterministic, no
