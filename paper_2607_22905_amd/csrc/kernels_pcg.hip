@@ -571,25 +571,27 @@ __global__ __launch_bounds__(1024) void k_pcg_coef(int kind, const double* __res
 // of A p_new dominate this product's traffic through the vector memory
 // path (seven neighbours, two vectors each, with p_new formed on the fly), so
 // the workgroup first forms p_new on its own rows and keeps the first
-// SubCap<NT> of them in LDS; a neighbour inside that range is then read from
+// SubCap<NT> of them (all rows of a subdomain of up to 1024 cells with 16
+// columns) in LDS; a neighbour inside that range is then read from
 // LDS, any other one (another subdomain, or beyond the cap) from z and p_old
 // as before.  The NT / 4 lanes of a row are neighbours, each with four
 // columns.  The ELL rows of the product are loaded one pass ahead: the first
 // pass's before p_new is formed, the next pass's while the current one is
 // multiplied.
-template <int NT> struct SubCap { static constexpr int v = 8192 / NT; };  // 64 KB of p_new
+template <int NT> struct SubCap { static constexpr int v = 16384 / NT; };  // 128 KB of p_new
+constexpr int kSpmvSubThreads = 1024;
 template <int NT, int MAXW>
-__global__ __launch_bounds__(512) void k_spmv_sub(
+__global__ __launch_bounds__(kSpmvSubThreads) void k_spmv_sub(
     int64_t n, int w, const int32_t* __restrict__ ec, const double* __restrict__ ev,
     const double* __restrict__ z, const double* __restrict__ pold, double* __restrict__ pnew,
     double* __restrict__ q, const int64_t* __restrict__ sub_ptr, const double* __restrict__ coef,
     double* __restrict__ pa, PcgShared* sh) {
   static_assert(NT == 8 || NT == 16, "k_spmv_sub: 8 or 16 columns");
-  constexpr int KG = 4, TR = NT / KG, NTHR = 512, RW = NTHR / TR;
+  constexpr int KG = 4, TR = NT / KG, NTHR = kSpmvSubThreads, RW = NTHR / TR;
   constexpr int CAP = SubCap<NT>::v;
   constexpr int RPA = CAP / RW;  // rows per thread forming p_new: the LDS rows in one pass
   __shared__ double ps[CAP * NT];
-  __shared__ double lds[8 * NT];
+  __shared__ double lds[(NTHR / 64) * NT];
   if (*(volatile const int32_t*)&sh->all_done) return;  // uniform
   const int s = blockIdx.x;
   const int g = threadIdx.x % TR, k0 = g * KG, rsub = threadIdx.x / TR;
@@ -974,7 +976,7 @@ hipError_t launch_pcg_spmv(DeviceState& d, int nr, int parity, hipStream_t s) {
     AM_NR_SWITCH(nr, if constexpr (NR >= 8) {
       am_launch(d, true, false, k_pcg_coef<NR>, dim3(NR), dim3(1024), s, 0, d.red.pd, d.m,
                 d.red.coef, d.sc, d.shared, parity);
-      am_launch(d, false, true, k_spmv_sub<NR, MW>, dim3(d.m), dim3(512), s, d.n, d.ell_w,
+      am_launch(d, false, true, k_spmv_sub<NR, MW>, dim3(d.m), dim3(kSpmvSubThreads), s, d.n, d.ell_w,
                 d.ell_col, d.ell_val, d.z, po, pn, d.q, d.sub_ptr, d.red.coef, d.red.pa, d.shared);
     } else {
       am_launch(d, true, true, k_spmv_p<NR, MW>, dim3(spmv_grid<NR>(d)), dim3(256), s, d.n,
