@@ -43,14 +43,14 @@ int64_t nd_max_rows(int nr_max) {
 }
 
 // Workgroup (block b, rows row0 .. row0 + 63 of it): the block's right-hand
-// side goes to LDS, then out = Sbb^{-1} rhs for those 64 rows, the four
-// waves taking a quarter of the block's columns each (nd_wave_product); their
+// side goes to LDS, then out = Sbb^{-1} rhs for those 64 rows, the eight
+// waves taking an eighth of the block's columns each (nd_wave_product); their
 // partial sums are added in wave order.  Pass 0 writes y_B (ND order), pass 1
 // subtracts S_BT eta_T from the right-hand side first (or, with from_y1,
 // takes that right-hand side from y1, where k_nd_rb formed it) and writes
 // eta_B in the original order.  Dynamic LDS: max(rows of the largest block,
-// 256) NR doubles.
-template <int NR> struct NdWaves { static constexpr int v = NR <= 2 ? 8 : 4; };
+// 512) NR doubles.
+template <int NR> struct NdWaves { static constexpr int v = 8; };
 
 template <int NR>
 __global__ __launch_bounds__(64 * NdWaves<NR>::v) void k_nd_blocks(
