@@ -52,6 +52,32 @@ int64_t nd_max_rows(int nr_max) {
 // 512) NR doubles.
 template <int NR> struct NdWaves { static constexpr int v = 8; };
 
+// x - sum_{q in [qb, qe)} val[q] vec[pos[q] NR + k], the terms subtracted in
+// q order; the positions, values and gathers of four couplings are issued
+// before their products, so a row's chain waits once per four couplings.
+template <int NR>
+__device__ __forceinline__ double nd_sub_couplings(double x, int64_t qb, int64_t qe,
+                                                   const int32_t* __restrict__ pos,
+                                                   const double* __restrict__ val,
+                                                   const double* __restrict__ vec, int k) {
+  int64_t q = qb;
+  for (; q + 4 <= qe; q += 4) {
+    int32_t c[4];
+    double a[4], y[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      c[u] = pos[q + u];
+      a[u] = val[q + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) y[u] = vec[(size_t)c[u] * NR + k];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) x = fma(-a[u], y[u], x);
+  }
+  for (; q < qe; ++q) x = fma(-val[q], vec[(size_t)pos[q] * NR + k], x);
+  return x;
+}
+
 template <int NR>
 __global__ __launch_bounds__(64 * NdWaves<NR>::v) void k_nd_blocks(
     int pass, int from_y1, int nwg, const int32_t* __restrict__ wg_blk,
@@ -89,8 +115,7 @@ __global__ __launch_bounds__(64 * NdWaves<NR>::v) void k_nd_blocks(
       const int64_t n = ord[o + j];
       double v = bpart[(size_t)(2 * n) * NR + k] + bpart[(size_t)(2 * n + 1) * NR + k];
       if (pass)
-        for (int64_t q = b_ptr[o + j]; q < b_ptr[o + j + 1]; ++q)
-          v = fma(-b_val[q], eta2[(size_t)b_top[q] * NR + k], v);
+        v = nd_sub_couplings<NR>(v, b_ptr[o + j], b_ptr[o + j + 1], b_top, b_val, eta2, k);
       rhs[t] = v;
     }
   }
@@ -149,9 +174,7 @@ __global__ __launch_bounds__(256) void k_nd_top(
       const int j = jb + t / NR, k = t % NR;
       const int64_t n = ord_top[j];
       double x = bpart[(size_t)(2 * n) * NR + k] + bpart[(size_t)(2 * n + 1) * NR + k];
-      for (int64_t q = t_ptr[j]; q < t_ptr[j + 1]; ++q)
-        x = fma(-t_val[q], y1[(size_t)t_pos[q] * NR + k], x);
-      r2[t] = x;
+      r2[t] = nd_sub_couplings<NR>(x, t_ptr[j], t_ptr[j + 1], t_pos, t_val, y1, k);
     }
     __syncthreads();
   }
@@ -213,9 +236,7 @@ __global__ __launch_bounds__(256) void k_nd_rt(int R, const int32_t* __restrict_
   const int k = (int)(t % NR);
   const int64_t n = ord_top[j];
   double x = bpart[(size_t)(2 * n) * NR + k] + bpart[(size_t)(2 * n + 1) * NR + k];
-  for (int64_t q = t_ptr[j]; q < t_ptr[j + 1]; ++q)
-    x = fma(-t_val[q], y1[(size_t)t_pos[q] * NR + k], x);
-  rt[t] = x;
+  rt[t] = nd_sub_couplings<NR>(x, t_ptr[j], t_ptr[j + 1], t_pos, t_val, y1, k);
 }
 
 // b_B - S_BT eta_T, one thread per (block row, column), into y1 (y_B is no
@@ -236,9 +257,7 @@ __global__ __launch_bounds__(256) void k_nd_rb(int64_t nrows, const int32_t* __r
   const int k = (int)(t % NR);
   const int64_t n = ord[j];
   double x = bpart[(size_t)(2 * n) * NR + k] + bpart[(size_t)(2 * n + 1) * NR + k];
-  for (int64_t q = b_ptr[j]; q < b_ptr[j + 1]; ++q)
-    x = fma(-b_val[q], eta2[(size_t)b_top[q] * NR + k], x);
-  rb[t] = x;
+  rb[t] = nd_sub_couplings<NR>(x, b_ptr[j], b_ptr[j + 1], b_top, b_val, eta2, k);
 }
 
 // Launch sequence.  1-2 columns: four launches, the coupling terms formed in
