@@ -267,7 +267,9 @@ __device__ __forceinline__ void bpart_sub_g(int s, int k0, int64_t n, const int6
                                             const double* __restrict__ mbf,
                                             const int64_t* __restrict__ bdst, const double* r,
                                             double* bpart, double* lds) {
-  constexpr int QB = KG <= 2 ? 8 : 4;  // slots per round
+  // MBF slots per round: six cover a box subdomain (one interface per face)
+  // in one round, with fewer registers than eight
+  constexpr int QB = KG <= 2 ? 6 : 4;
   const int64_t base = sub_ptr[s];
   const int N = (int)(sub_ptr[s + 1] - base);
   const int64_t i0 = isub_ptr[s];
@@ -320,7 +322,9 @@ __global__ __launch_bounds__(256) void k_update_xr(
   // two rows per thread cover a 512-cell subdomain in one pass with half the
   // registers of four (more workgroups resident where there are many)
   constexpr int RPT = 2;
-  constexpr int QB = KG <= 2 ? 8 : 4;
+  // MBF slots per round as in bpart_sub_g (six: one round for a box
+  // subdomain; 91 -> 84 registers with one column)
+  constexpr int QB = KG <= 2 ? 6 : 4;
   __shared__ double lds[4 * 32];
   const int s = blockIdx.x / TR, g = blockIdx.x % TR, k0 = g * KG;
   const int done_flag = *(volatile const int32_t*)&sh->all_done;
