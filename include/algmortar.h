@@ -339,10 +339,13 @@ am_status algmortar_time_kernel(am_handle h, int32_t kernel, int32_t nrhs, int32
 /* Batching form: the wave layout of the local kernel (groups of right-hand
  * sides x column splits of each block pass) is chosen per right-hand-side
  * count by an autotuner that times every candidate layout on this handle's
- * subdomains.  It runs, and synchronizes, on the first algmortar_apply or
- * algmortar_pcg with that count (or here).  choice: host (out), index of the
- * chosen candidate; ncand: host (out), number of candidates; us: host (out,
- * may be NULL), double[4], average launch time of each candidate in us.
+ * subdomains as a solve runs it (with the PCG dot products, on a freshly
+ * initialised PCG state that the next algmortar_pcg initialises again; the
+ * candidates take turns over three rounds).  It runs, and synchronizes, on
+ * the first algmortar_apply or algmortar_pcg with that count (or here).
+ * choice: host (out), index of the chosen candidate; ncand: host (out),
+ * number of candidates; us: host (out, may be NULL), double[4], each
+ * candidate's average launch time in us over its fastest round.
  * The layouts add the waves' partial vectors in different orders, so two
  * handles whose timings chose differently can differ in the last bits; with
  * the environment variable ALGMORTAR_TILE=c, candidate c (clamped to the
