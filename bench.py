@@ -431,12 +431,16 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "kernel": ("k_localt (tile sweeps, fused interface solve, reconstruction)"
+                     "kernel": (("k_localt_mf + k_localt_mf2 (16 RHS on the matrix cores: tile sweeps, "
+                                 "reconstruction; one launch per window bucket)" if nrhs == 16 else
+                                 "k_localt (tile sweeps, fused interface solve, reconstruction)")
                                 if smooth is None else
                                 "k_localt on the smoothing blocks (block-Jacobi solves)"),
                      "avg_launch_us": k_ms * 1e3, "launches": k_launches,
                      "bytes_per_launch": k_bytes,
-                     "timing": ("HIP events attached to the launches of a profiled solve (plain launches, hipExtLaunchKernelGGL)"
+                     "timing": ("HIP events attached to the launches of a profiled solve (plain launches, "
+                                "hipExtLaunchKernelGGL); with two window buckets, events on the library's stream "
+                                "before the fork and after the join of the pair running side by side"
                                 if smooth is None else "replayed alone (20 back-to-back launches)"),
                      "isolated_avg_launch_us": iso["local"] * 1e3},
         "other_kernels": others,

@@ -1606,8 +1606,9 @@ hipError_t localt_shape(DeviceState& d, const double* r, double* z, const double
   // With both window buckets populated, the window-128 bucket (few, long
   // workgroups) runs on a second stream beside the window-64 one: a fork and
   // a join on events, which graph capture records as two parallel branches.
-  // A profiled solve keeps the two launches in order on one stream.
-  const bool fork = nb0 > 0 && nb1 > 0 && d.side && !d.prof_ev[0] && !d.prof_ev[1];
+  // In a profiled solve the operation's two events are recorded on st before
+  // the fork and after the join, so they time the pair as it runs.
+  const bool fork = nb0 > 0 && nb1 > 0 && d.side;
   auto launch_bucket = [&](int bk, hipStream_t s, bool first, bool last) {
     const int nb = bk == 0 ? nb0 : nb1;
     const unsigned off = bk == 0 ? 0u : (unsigned)nb0;  // rows of the partials
@@ -1657,13 +1658,30 @@ hipError_t localt_shape(DeviceState& d, const double* r, double* z, const double
     }
   };
   if (fork) {
-    hipError_t e = hipEventRecord(d.ev_fork, st);
+    const hipEvent_t p0 = d.prof_ev[0], p1 = d.prof_ev[1];
+    hipError_t e = hipSuccess;
+    if (p0) {
+      if ((e = hipEventRecord(p0, st)) != hipSuccess) return e;
+      d.prof_used[0] = true;
+    }
+    d.prof_ev[0] = d.prof_ev[1] = nullptr;  // no events on the launches themselves
+    e = hipEventRecord(d.ev_fork, st);
     if (e == hipSuccess) e = hipStreamWaitEvent(d.side, d.ev_fork, 0);
+    if (e == hipSuccess) {
+      launch_bucket(1, d.side, false, false);
+      e = hipEventRecord(d.ev_join, d.side);
+    }
+    if (e == hipSuccess) {
+      launch_bucket(0, st, false, false);
+      e = hipStreamWaitEvent(st, d.ev_join, 0);
+    }
+    d.prof_ev[0] = p0;
+    d.prof_ev[1] = p1;
     if (e != hipSuccess) return e;
-    launch_bucket(1, d.side, false, false);
-    if ((e = hipEventRecord(d.ev_join, d.side)) != hipSuccess) return e;
-    launch_bucket(0, st, false, false);
-    if ((e = hipStreamWaitEvent(st, d.ev_join, 0)) != hipSuccess) return e;
+    if (p1) {
+      if ((e = hipEventRecord(p1, st)) != hipSuccess) return e;
+      d.prof_used[1] = true;
+    }
   } else {
     if (nb0 > 0) launch_bucket(0, st, true, nb1 == 0);
     if (nb1 > 0) launch_bucket(1, st, nb0 == 0, true);
