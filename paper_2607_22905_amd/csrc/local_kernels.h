@@ -398,8 +398,9 @@ constexpr int kPreQ = 8;  // MBF columns whose values are fetched a block ahead
 // The 64 columns of block b (C chunks of 64 rows) are contiguous in Lc: the
 // tile of block b holds Lt_bb^{-1} below its diagonal (chunk b % C) and the
 // couplings L_{b+c,b} to the next C blocks in the remaining entries.  A
-// workgroup stages each tile in LDS once per sweep (16-byte coalesced loads,
-// one tile ahead, double buffered); the forward sweep reads it by columns
+// workgroup stages each tile in LDS once per sweep (16-byte coalesced loads
+// held in registers one or two tiles ahead, double buffered in LDS); the
+// forward sweep reads it by columns
 // and the backward sweep by rows (the transpose) from the same tile.  Every
 // step of a pass is independent of the others: the W waves of a group take
 // 64/W columns each and their partial vectors are summed in LDS in wave
@@ -885,8 +886,11 @@ __global__ __launch_bounds__(64 * G * W) void k_localt(
 // arithmetic of the vector-unit kernel for those factors.  Both take lane l's
 // operands as A[l % 16][l / 16] and B[l / 16][l % 16]; the FP64 result is
 // D[l / 16 + 4 v][l % 16], the FP32 one D[4 (l / 16) + v][l % 16] (v < 4).
-// The block vectors (64 rows x 16) live in LDS (two buffers, pitch 17); the
-// tiles are staged as in k_localt.
+// With BF16 factors and BFOP, the products are BF16 x BF16 with FP32
+// accumulation instead (v_mfma_f32_16x16x16bf16_1k, the block vectors
+// rounded to BF16; see mf_pass).  The block vectors (64 rows x 16) live in
+// LDS (two buffers, pitch 17); each tile goes through registers (loaded
+// while the previous one is in use) into one LDS buffer.
 //   forward  y_b = t_b + Nlow_b t_b,   out_b = dinv y_b,
 //            t_{b+1} = r_{b+1} - U_b y_b
 //   backward s_b = out_b - U_b^T x_{b+1},   x_b = s_b + Nlow_b^T s_b,
