@@ -304,17 +304,25 @@ def test_c3_full_size_batched_pcg():
     h1.close()
 
 
-def test_pcg_profile_matches_pcg():
+@pytest.mark.parametrize("case,nrhs", [("layered", 1), ("bisect", 16)])
+def test_pcg_profile_matches_pcg(case, nrhs):
     """The event-timed solve runs the same kernels in the same order: the
     iterate is bitwise that of the graph-launched solve, and every counted
-    launch has a positive duration."""
-    A, part, m, b, ora = setup_case("layered")
-    h = am.AlgMortar(A, part, m)
-    x1, info1, _ = h.pcg(gpu(b), 1e-10)
-    x2, info2, prof = h.pcg_profile(gpu(b), 1e-10)
+    launch has a positive duration.  With 16 columns on the bisection
+    partition the two window buckets' matrix-core kernels run side by side
+    on two streams in both solves, and the profiled one times the pair."""
+    A, part, m, b, ora = setup_case(case)
+    if nrhs == 1:
+        h = am.AlgMortar(A, part, m)
+        rhs = gpu(b)
+    else:
+        h = am.AlgMortar(A, part, m, separate_iface=True, max_nrhs=nrhs)
+        rhs = gpu(np.random.default_rng(nrhs).standard_normal((nrhs, A.n)))
+    x1, info1, _ = h.pcg(rhs, 1e-10)
+    x2, info2, prof = h.pcg_profile(rhs, 1e-10)
     assert np.array_equal(cpu(x1), cpu(x2))
-    assert info1[0]["iterations"] == info2[0]["iterations"]
-    its = info2[0]["iterations"]
+    assert [i["iterations"] for i in info1] == [i["iterations"] for i in info2]
+    its = max(i["iterations"] for i in info2)
     for name in ("local", "spmv", "update"):
         ms, cnt = prof[name]
         assert its - 2 <= cnt <= its + 1 and ms > 0.0
