@@ -210,8 +210,11 @@ def precision_forms(P, part, m, b, x64, args, v64, its64):
     res = {}
     nrhs = P.nrhs
     forms = [("fp32", "fp32", {}), ("bf16", "bf16", {})]
-    if nrhs == 16:
-        forms.append(("bf16_products", "bf16", {"bf16_products": True}))
+    if nrhs in (1, 16):
+        # BF16 x BF16 products on the matrix cores (with one right-hand side:
+        # column 0 of each tile); the flag needs the interface solve as its
+        # own launches
+        forms.append(("bf16_products", "bf16", {"bf16_products": True, "separate_iface": True}))
     for name, prec, kw in forms:
         h = am.AlgMortar(P.A, part, m, prec=prec, graph=not args.no_graph, max_nrhs=nrhs, **kw)
         x = torch.empty_like(b)

@@ -106,15 +106,18 @@ typedef struct {
  * algmortar_set_inexact.  The outer PCG then uses the flexible Polak-Ribiere
  * beta (the preconditioner depends on its argument). */
 #define AM_FLAG_INEXACT_IFACE 8u
-/* precision form with BF16 factors (local_prec AM_BF16) and 16 right-hand
- * sides, where the local solves run on the matrix cores (the interface solve
- * as its own launches): multiply the BF16 factor tiles by the block vectors
- * rounded to BF16 (round to nearest even), BF16 x BF16 products with FP32
- * accumulation (v_mfma_f32_16x16x16bf16_1k), instead of the default FP32 x
- * FP32 products of the widened factors.  The preconditioner then carries
- * 8-bit block vectors into every factor product; the outer PCG is the
- * flexible one, as for every reduced precision.  Ignored in every other
- * case. */
+/* precision form with BF16 factors (local_prec AM_BF16), the interface
+ * solve as its own launches, and either 16 right-hand sides (where the local
+ * solves run on the matrix cores) or one right-hand side with every
+ * subdomain's band within 64 rows: multiply the BF16 factor tiles by the
+ * block vectors rounded to BF16 (round to nearest even), BF16 x BF16
+ * products with FP32 accumulation on the matrix cores
+ * (v_mfma_f32_16x16x16bf16_1k; one right-hand side takes column 0 of each
+ * 16-column tile), instead of the default FP32 x FP32 products of the
+ * widened factors (matrix cores with 16 right-hand sides, vector units with
+ * one).  The preconditioner then carries 8-bit block vectors into every
+ * factor product; the outer PCG is the flexible one, as for every reduced
+ * precision.  Ignored in every other case. */
 #define AM_FLAG_BF16_PRODUCTS 16u
 
 typedef struct {

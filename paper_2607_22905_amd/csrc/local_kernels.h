@@ -984,7 +984,9 @@ __global__ __launch_bounds__(256) void k_localt_mf(
     const int32_t* __restrict__ isub_list, const int64_t* __restrict__ mbf_off,
     const double* __restrict__ mbf, const double* __restrict__ eta, const double* __restrict__ qv,
     double* __restrict__ partial, unsigned blk_off, PcgShared* sh, int64_t nrows) {
-  static_assert(NT == 16, "one 16-column matrix-core tile");
+  // 16 right-hand sides fill the 16 columns of a matrix-core tile; one
+  // right-hand side takes column 0 (lanes of the other columns carry zeros)
+  static_assert(NT == 16 || NT == 1, "one 16-column matrix-core tile");
   using AT = typename AccT<FT>::T;  // arithmetic type: FP64, else FP32
   using V = typename MfAcc<AT>::V;
   constexpr int PITCH = 65;
@@ -995,7 +997,7 @@ __global__ __launch_bounds__(256) void k_localt_mf(
   constexpr int PD = 1;  // one tile ahead in registers (two workgroups per CU)
   __shared__ AT tile[CH];  // one buffer: two workgroups fit a CU
   __shared__ AT vb[2][64 * kMfVP];
-  __shared__ AT eta_s[64 * NT];
+  __shared__ AT eta_s[TileMaxNi<NT>::v * NT];
   __shared__ double dots[4][2 * NT];
 
   const int s = subs[blockIdx.x];
@@ -1009,6 +1011,7 @@ __global__ __launch_bounds__(256) void k_localt_mf(
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane % 16, lk = lane / 16;
+  const bool colok = li < NT;  // this lane's column is a right-hand side
   const int64_t i0 = isub_ptr[s];
   const int ns = mode >= 1 ? (int)(isub_ptr[s + 1] - i0) : 0;
   const double* P = mbf + mbf_off[s];
@@ -1040,10 +1043,10 @@ __global__ __launch_bounds__(256) void k_localt_mf(
     eta_s[t] = (AT)eta[(size_t)isub_list[i0 + t / NT] * NT + (t % NT)];
   tile_store(0);
   if (1 < NB) tile_load(1, 0);
-  // t_0 = r of block 0
-  for (int e = threadIdx.x; e < 64 * NT; e += NTHR) {
-    const int row = e / NT, k = e % NT;
-    vb[0][row * kMfVP + k] = row < N ? (AT)rin[vi(row, k)] : AT(0);
+  // t_0 = r of block 0 (columns beyond NT: zero)
+  for (int e = threadIdx.x; e < 64 * 16; e += NTHR) {
+    const int row = e / 16, k = e % 16;
+    vb[0][row * kMfVP + k] = (row < N && k < NT) ? (AT)rin[vi(row, k)] : AT(0);
   }
   __syncthreads();
 
@@ -1055,7 +1058,7 @@ __global__ __launch_bounds__(256) void k_localt_mf(
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = j0 + 64 + drow(v);
-      rn[v] = row < N ? (AT)rin[vi(row, li)] : AT(0);
+      rn[v] = (row < N && colok) ? (AT)rin[vi(row, li)] : AT(0);
       dvl[v] = dv[j0 + drow(v)];
     }
     const AT* T = tile;
@@ -1073,7 +1076,7 @@ __global__ __launch_bounds__(256) void k_localt_mf(
     for (int v = 0; v < 4; ++v) {
       vb[1][drow(v) * kMfVP + li] = acc[v];
       const int row = j0 + drow(v);
-      if (row < N) out[vi(row, li)] = (double)(acc[v] * dvl[v]);
+      if (row < N && colok) out[vi(row, li)] = (double)(acc[v] * dvl[v]);
     }
     __syncthreads();
     // pass A: t_{b+1} = r_{b+1} - U y
@@ -1102,7 +1105,7 @@ __global__ __launch_bounds__(256) void k_localt_mf(
   // ---- backward sweep: tile NB-1 is still in LDS ----
   if (NB > 1) tile_load(NB - 2, 0);
   // x_{NB} = 0
-  for (int e = threadIdx.x; e < 64 * NT; e += NTHR) vb[1][(e / NT) * kMfVP + e % NT] = AT(0);
+  for (int e = threadIdx.x; e < 64 * 16; e += NTHR) vb[1][(e / 16) * kMfVP + e % 16] = AT(0);
   __syncthreads();
   double rz = 0.0, qz = 0.0;  // column li of this lane's rows
   auto bwd_body = [&](const int b, auto parc) {
@@ -1114,7 +1117,7 @@ __global__ __launch_bounds__(256) void k_localt_mf(
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = j0 + drow(v);
-      const bool ok = row < N;
+      const bool ok = row < N && colok;
       vv[v] = ok ? (AT)out[vi(row, li)] : AT(0);
       rp[v] = (ok && mode == 2) ? rin[vi(row, li)] : 0.0;
       qp[v] = (ok && mode == 2) ? qv[vi(row, li)] : 0.0;
@@ -1156,19 +1159,19 @@ __global__ __launch_bounds__(256) void k_localt_mf(
     for (int c = 0; c < NPA; ++c) {
       if (4 * c >= ns) break;  // uniform
       const int q = 4 * c + lk;
-      const AT e = q < ns ? eta_s[q * NT + li] : AT(0);
+      const AT e = (q < ns && colok) ? eta_s[q * NT + li] : AT(0);
       acc = mf4(pa[c], e, acc);
     }
     for (int c = NPA; 4 * c < ns; ++c) {
       const int q = 4 * c + lk;
       const AT av = (q < ns && ra < N) ? (AT)P[(size_t)q * N + ra] : AT(0);
-      const AT e = q < ns ? eta_s[q * NT + li] : AT(0);
+      const AT e = (q < ns && colok) ? eta_s[q * NT + li] : AT(0);
       acc = mf4(av, e, acc);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = j0 + drow(v);
-      if (row < N) {
+      if (row < N && colok) {
         const double zv = (double)acc[v];
         out[vi(row, li)] = zv;
         rz = fma(rp[v], zv, rz);
@@ -1197,7 +1200,7 @@ __global__ __launch_bounds__(256) void k_localt_mf(
   rz += __shfl_xor(rz, 32, 64);
   qz += __shfl_xor(qz, 16, 64);
   qz += __shfl_xor(qz, 32, 64);
-  if (lane < 16) {
+  if (lane < NT) {
     dots[w][lane] = rz;
     dots[w][NT + lane] = qz;
   }
@@ -1643,6 +1646,14 @@ hipError_t localt_shape(DeviceState& d, const double* r, double* z, const double
             go_mf(k_localt_mf<FT, 16, kBf>);
           else
             go_mf(k_localt_mf<FT, 16, false>);
+        }
+      }
+      // one right-hand side with BF16 x BF16 products: column 0 of the
+      // matrix-core tiles, where every subdomain is in the window-64 bucket
+      if constexpr (NT == 1 && kBf) {
+        if (!d.fuse_eta && d.bf16_ops && nb1 == 0) {
+          mf = true;
+          go_mf(k_localt_mf<FT, 1, true>);
         }
       }
       if (!mf) go(k_localt<FT, 1, NT, S::G, S::W>, 64 * S::G * S::W);

@@ -402,6 +402,34 @@ def test_matrix_core_16_rhs_reduced_precision(prec):
     hm.close()
 
 
+@pytest.mark.parametrize("case", ["c1", "ragged3d", "layered"])
+def test_bf16_products_one_rhs(case):
+    """One right-hand side with BF16 factors and BF16 x BF16 products on the
+    matrix cores (column 0 of each 16-column tile; AM_FLAG_BF16_PRODUCTS,
+    interface solve as its own launches, every subdomain in window 64).  The
+    apply is within 0.05 of the oracle's FP64 apply and at least 1e-5 from the
+    vector-unit BF16 form with FP32 products (the flag is in effect); PCG
+    (flexible, FP64 outer loop) at tol 1e-10 within 1e-8 of the oracle's
+    solution, true residual <= 1e-9, iterations at most twice the oracle's
+    plus 10."""
+    A, part, m, b, ora = setup_case(case)
+    r = np.random.default_rng(17).standard_normal(A.n)
+    zo = ora.apply(r)
+    hb = am.AlgMortar(A, part, m, prec="bf16", separate_iface=True, bf16_products=True)
+    hf = am.AlgMortar(A, part, m, prec="bf16", separate_iface=True)
+    zb = cpu(hb.apply(gpu(r)))
+    zf = cpu(hf.apply(gpu(r)))
+    hf.close()
+    assert rel(zb, zo) <= 5e-2 and rel(zb, zf) >= 1e-5, (rel(zb, zo), rel(zb, zf))
+    x, info, _ = hb.pcg(gpu(b), 1e-10)
+    As = A.to_scipy()
+    ref = pcg(lambda v: As @ v, b, ora.apply, 1e-10)
+    assert rel(cpu(x), ref.x) <= 1e-8
+    assert info[0]["converged"] == 1 and info[0]["true_rel_res"] <= 1e-9
+    assert info[0]["iterations"] <= 2 * ref.iterations + 10
+    hb.close()
+
+
 def test_bf16_products_16_rhs():
     """BF16 factors with BF16 x BF16 products on the matrix cores (block
     vectors rounded to BF16, FP32 accumulation; AM_FLAG_BF16_PRODUCTS), 16
