@@ -360,8 +360,9 @@ am_status algmortar_time_kernel(am_handle h, int32_t kernel, int32_t nrhs, int32
  * choice) and read back by later handles and processes, which then use the
  * recorded layout without timing (us holds zeros): the same results as the
  * process that timed it.  16 right-hand sides with the interface solve as
- * its own launches run matrix-core kernels of a single layout: choice 0,
- * ncand 1, nothing timed. */
+ * its own launches, and one right-hand side under AM_FLAG_BF16_PRODUCTS
+ * with every subdomain's band within 64 rows, run matrix-core kernels of a
+ * single layout: choice 0, ncand 1, nothing timed. */
 am_status algmortar_tile_choice(am_handle h, int32_t nrhs, int32_t* choice, int32_t* ncand,
                                 double* us);
 

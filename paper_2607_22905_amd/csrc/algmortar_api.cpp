@@ -865,15 +865,22 @@ static am_status check_vec_args(am_handle h, const void* a, const void* b, int32
 // work vectors of this handle) and keeps the fastest for the handle's later
 // applies and solves.  Runs once per right-hand-side count, outside any graph
 // capture.
+// The local kernel has a single layout: 16 right-hand sides with the
+// interface solve as its own launches, or one right-hand side with BF16 x
+// BF16 products where every subdomain is in the window-64 bucket (the
+// matrix-core kernels in both cases).
+static bool single_layout(const DeviceState& d, int nr) {
+  if (d.fuse_eta) return false;
+  return nr == 16 || (nr == 1 && d.bf16_ops && d.bucket_sub[1].empty());
+}
+
 static am_status autotune_tiles(am_handle h, int nr) {
   DeviceState& d = h->d;
   const int slot = tile_slot(nr);
   if (d.tile_cand[slot] >= 0) return AM_OK;
   const int nc = tile_candidates(nr);
-  // 16 right-hand sides with the interface solve as its own launches run the
-  // matrix-core kernels in both window buckets, which have one layout: nothing
-  // to choose
-  if (nr == 16 && !d.fuse_eta) {
+  // the matrix-core kernels have one layout: nothing to choose
+  if (single_layout(d, nr)) {
     d.tile_cand[slot] = 0;
     return AM_OK;
   }
@@ -960,7 +967,7 @@ am_status algmortar_tile_choice(am_handle h, int32_t nrhs, int32_t* choice, int3
   if (s != AM_OK) return s;
   const int slot = tile_slot(nr);
   *choice = h->d.tile_cand[slot];
-  *ncand = (nr == 16 && !h->d.fuse_eta) ? 1 : tile_candidates(nr);
+  *ncand = single_layout(h->d, nr) ? 1 : tile_candidates(nr);
   if (us)
     for (int c = 0; c < *ncand; ++c) us[c] = h->d.tile_us[slot][c];
   return AM_OK;

@@ -68,3 +68,22 @@ def test_sixteen_columns_one_layout():
     ch, us = h.tile_choice(16)
     assert ch == 0 and us == [0.0]
     h.close()
+
+
+def test_one_column_bf16_products_one_layout():
+    """One column under BF16 x BF16 products, every subdomain in window 64
+    and the interface solve as its own launches: the matrix-core kernel, one
+    layout, nothing timed; without the flag the layouts are timed."""
+    import torch  # noqa: F401
+    sys.path.insert(0, ROOT)
+    import paper_2607_22905_amd as am
+    from tests.test_gpu_parity import _case
+    A, part, m, b = _case("layered")
+    h = am.AlgMortar(A, part, m, prec="bf16", separate_iface=True, bf16_products=True)
+    ch, us = h.tile_choice(1)
+    assert ch == 0 and us == [0.0]
+    h.close()
+    h = am.AlgMortar(A, part, m, prec="bf16", separate_iface=True)
+    ch, us = h.tile_choice(1)
+    assert len(us) > 1 and all(u > 0.0 for u in us)
+    h.close()
